@@ -1,0 +1,144 @@
+/*
+ * cylspec -- spectral Poisson and heat solver in the closed cylinder on MI355X.
+ *
+ * Method: D. Darrow, "A Quasi-Optimal Spectral Solver for the Heat and Poisson
+ * Equations in a Closed Cylinder" (arXiv 2206.04827).  A field on the doubled
+ * Chebyshev-Chebyshev-Fourier grid (Section 2, Definition "grid") is moved to
+ * CCF coefficients by DCT-I in r, DCT-I in z and a DFT in theta (Section 2);
+ * each Fourier mode then obeys its own sparse Sylvester equation
+ * (Section 3, eq. HelmholtzMatEqn), which is solved by ADI with Zolotarev
+ * shifts (Section 3, Algorithm 1 and the shift formulas after it).
+ *
+ * Conventions for every call below:
+ *  - All array arguments are DEVICE pointers to FP64 data, used on the plan's
+ *    HIP stream.  The caller allocates and frees them; inputs and outputs must
+ *    not alias.  Every call returns after enqueueing work; results are valid
+ *    after the stream has synchronised.
+ *  - Value space: real array [n_theta][n_z][n_r], r fastest.  Element (l,k,j)
+ *    is the value at the grid point of Definition "grid":
+ *        r_j = cos((n_r - j - 1) pi / (n_r - 1)),  z_k likewise,
+ *        theta_l = (2 l - n_theta) pi / n_theta.
+ *  - Coefficient space: complex interleaved (re, im) array
+ *    [floor(n_theta/2) + 1][n_z][n_r], r fastest.  Slot (w,k,j) holds the
+ *    coefficient of T_j(r) T_k(z) e^{i w theta} (Section 2, the CCF
+ *    polynomial) of a REAL field, w = 0..floor(n_theta/2); negative w follow by
+ *    conjugation.  For even n_theta the slot w = n_theta/2 holds the paper's
+ *    w = -n_theta/2 coefficient (the same function on the grid).  Imaginary
+ *    parts of the w = 0 and Nyquist slots are ignored on input and written as 0.
+ *  - Boundary data: homogeneous Dirichlet at r = +-1 and z = +-1 unless a lift
+ *    field is given.  A lift is any field (same space as the data) whose values
+ *    on the boundary grid points are the Dirichlet data; only those boundary
+ *    values affect the result.  The paper states no boundary closure for these
+ *    two problems; this tau/Dirichlet closure is the library's reading.
+ *  - Errors: argument checks are synchronous and enqueue nothing.  A failed
+ *    call returns a CYL_E_* code; cyl_last_error() gives a thread-local
+ *    description.  HIP runtime failures map to CYL_E_HIP.
+ *  - Handles are not thread safe.
+ */
+#ifndef CYLSPEC_H
+#define CYLSPEC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cyl_plan_s* cyl_plan_t;
+typedef struct cyl_heat_s* cyl_heat_t;
+
+enum {
+    CYL_OK = 0,
+    CYL_E_INVALID_ARG = 1,
+    CYL_E_UNSUPPORTED = 2,
+    CYL_E_OUT_OF_MEMORY = 3,
+    CYL_E_HIP = 4,
+    CYL_E_NOT_CONVERGED = 5,
+    CYL_E_INTERNAL = 6
+};
+
+enum { CYL_SPACE_VALUE = 0, CYL_SPACE_COEFF = 1 };
+
+/* Filled by cyl_poisson_solve when a host pointer is given (this synchronises
+ * the stream).  resid_ratio = ||E - L(X)||_2 / ||E||_2 over all modes, where
+ * L(X) = A X B + C X D is the per-mode operator of eq. (HelmholtzMatEqn). */
+typedef struct {
+    int J_max;          /* most ADI iterations of any mode (per pass)        */
+    int J_min;          /* fewest ADI iterations of any mode (per pass)      */
+    int passes;         /* 1, or 2 when a residual-correction pass was run   */
+    int reserved;
+    double resid_ratio;
+    double adi_iterations_mean; /* mean J over real mode planes, per pass   */
+} cyl_solve_info;
+
+/* Accumulated device time per phase since profiling was enabled (ms), and the
+ * number of launches recorded for each.  Filled by cyl_plan_get_profile. */
+typedef struct {
+    double ms_transform_fwd, ms_rhs, ms_adi, ms_residual, ms_recombine,
+           ms_transform_inv, ms_heat_rhs, ms_project;
+    int n_transform_fwd, n_rhs, n_adi, n_residual, n_recombine,
+        n_transform_inv, n_heat_rhs, n_project;
+} cyl_profile;
+
+/* Create a plan for an n_r x n_z x n_theta grid (Definition "grid").
+ * Requires 4 <= n_r, n_z <= 1025 and 1 <= n_theta <= 4096.  The plan owns the
+ * operator bands of Section 3 for every wavenumber and a device workspace;
+ * hip_stream (a hipStream_t, NULL = the default stream) is used for all work.
+ * Ownership: the caller destroys the plan with cyl_plan_destroy. */
+int cyl_plan_create(cyl_plan_t* plan, int n_r, int n_z, int n_theta, void* hip_stream);
+int cyl_plan_destroy(cyl_plan_t plan);
+
+/* Values -> coefficients (Section 2: DCT-I along r, DCT-I along z, DFT along
+ * theta).  values: [n_theta][n_z][n_r]; coeffs: complex [n_theta/2+1][n_z][n_r]. */
+int cyl_transform_fwd(cyl_plan_t plan, const double* values, double* coeffs);
+/* Coefficients -> values on the grid (the inverse of cyl_transform_fwd). */
+int cyl_transform_inv(cyl_plan_t plan, const double* coeffs, double* values);
+
+/* Solve nabla^2 u = f in the cylinder (Section 3, eq. HelmholtzMatEqn without
+ * time terms), u = bc on the boundary (bc_lift == NULL: homogeneous).
+ * space: CYL_SPACE_VALUE or CYL_SPACE_COEFF for f, bc_lift and u alike.
+ * adi_tol: the ADI tolerance eps, 1e-15 <= eps <= 1e-2; the number of ADI
+ * iterations per mode is J = ceil(ln(16 gamma) ln(4/eps) / pi^2).  The first
+ * call with a new adi_tol builds and uploads that tolerance's shift tables
+ * (host work and device allocation); later calls allocate nothing.
+ * info: NULL, or a host struct to fill (synchronises; CYL_E_NOT_CONVERGED if
+ * the result is not finite or resid_ratio > 1e3 * max(adi_tol, 1e-12)). */
+int cyl_poisson_solve(cyl_plan_t plan, int space, const double* f, const double* bc_lift,
+                      double* u, double adi_tol, cyl_solve_info* info);
+
+/* Heat equation (d_t - alpha nabla^2) T = g (Section 3), advanced by BDF of
+ * order bdf_order in {1, 4} with step dt (kappa^(1) = dt,
+ * kappa^(4) = 12 dt / 25); g and the boundary data are time independent.
+ * history: host array of bdf_order device pointers to the fields T(t),
+ * T(t-dt), ... (newest first) in the given space.  The handle copies what it
+ * needs; the caller's arrays may be freed after the call.  The handle owns its
+ * device state until cyl_heat_destroy. */
+int cyl_heat_create(cyl_heat_t* h, cyl_plan_t plan, double alpha, double dt, int bdf_order,
+                    double adi_tol, int space, const double* const* history,
+                    const double* g, const double* bc_lift);
+/* Advance n_steps >= 0 steps (enqueue only; allocates nothing). */
+int cyl_heat_step(cyl_heat_t h, int n_steps);
+/* Write the newest temperature field to T_out in the given space. */
+int cyl_heat_read(cyl_heat_t h, int space, double* T_out);
+int cyl_heat_destroy(cyl_heat_t h);
+
+/* Host-only (needs no GPU): the ADI parameters the plan would use for
+ * wavenumber w of an n_r x n_z grid.  kappa_alpha = 0 selects the Poisson
+ * pencil, kappa_alpha > 0 the heat pencil of eq. (HelmholtzMatEqn).
+ * bounds4 receives the enclosing spectral intervals [a, b] and [c, d] of
+ * Section 3 (a, b for C^-1 A; c, d for -D B^-1); J receives the iteration
+ * count; u and v (capacity cap) receive the shifts u_j (first half-step, in
+ * [c, d]) and v_j (second half-step, in [a, b]). */
+int cyl_adi_parameters(int n_r, int n_z, int w, double kappa_alpha, double adi_tol,
+                       double* bounds4, int* J, double* u, double* v, int cap);
+
+/* Profiling: record HIP events around every phase on the plan's stream. */
+int cyl_plan_set_profiling(cyl_plan_t plan, int enable);
+/* Synchronise, return and reset the accumulated per-phase device times. */
+int cyl_plan_get_profile(cyl_plan_t plan, cyl_profile* out);
+
+const char* cyl_status_string(int status);
+const char* cyl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CYLSPEC_H */

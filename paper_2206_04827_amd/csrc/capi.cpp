@@ -1,0 +1,744 @@
+// C ABI of the cylinder solver (declared in include/cylspec.h).
+#include "../../include/cylspec.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace cyl {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Failure {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Failure{code, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+            fail(CYL_E_OUT_OF_MEMORY, std::string(what) + ": " + hipGetErrorString(e));
+        fail(CYL_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+template <typename F>
+int guarded(F&& body) {
+    try {
+        body();
+        return CYL_OK;
+    } catch (const Failure& f) {
+        g_last_error = f.msg;
+        return f.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return CYL_E_OUT_OF_MEMORY;
+    } catch (const std::exception& e) {
+        g_last_error = std::string("internal error: ") + e.what();
+        return CYL_E_INTERNAL;
+    }
+}
+
+// Owned device allocation.
+struct DevMem {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    ~DevMem() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b) {
+        release();
+        if (b == 0) b = 8;
+        hip_check(hipMalloc(&p, b), "hipMalloc");
+        bytes = b;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+template <typename T>
+void upload(DevMem& m, const std::vector<T>& v) {
+    m.alloc(v.size() * sizeof(T));
+    if (!v.empty()) hip_check(hipMemcpy(m.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+}
+
+struct DftOwned {
+    DftTables t;
+    DevMem tw, chirp, bhat;
+    DftDev view{};
+    void build(int L) {
+        t = build_dft_tables(L);
+        upload(tw, t.tw);
+        if (t.bluestein) { upload(chirp, t.chirp); upload(bhat, t.bhat); }
+        view.L = t.L; view.Nb = t.Nb; view.log2Nb = t.log2Nb; view.bluestein = t.bluestein ? 1 : 0;
+        view.tw = tw.as<double2>();
+        view.chirp = t.bluestein ? chirp.as<double2>() : nullptr;
+        view.bhat = t.bluestein ? bhat.as<double2>() : nullptr;
+    }
+};
+
+// ADI tables, block descriptors and operator-apply records of one pencil.
+struct Setup {
+    AdiSetup h;
+    int passes = 1;
+    DevMem rtab, ztab, vmu, blocks, atab;
+    std::vector<BlockDesc> hblocks;
+};
+
+enum Phase { PH_FWD, PH_RHS, PH_ADI, PH_RES, PH_REC, PH_INV, PH_HRHS, PH_PROJ, PH_COUNT };
+
+}  // namespace
+}  // namespace cyl
+
+using namespace cyl;
+
+struct cyl_plan_s {
+    int m = 0, n = 0, p = 0;
+    hipStream_t stream = nullptr;
+    Geometry geo;
+    DirOps rops, zops;
+    DftOwned dr, dz, dth;
+    DevMem pre_fr, post_fr, pre_ir, post_ir, pre_fz, post_fz, pre_iz, post_iz;
+    DevMem t_r2, t_a0, t_s10, t_c02, t_d2;
+    RhsTables rhs{};
+    DevMem plane_of, ztabA, atab_proj;
+    DevMem planesA, planesB, E, X, R, state, acc;
+    bool use_lds = false;
+    int adi_threads = 64;
+    size_t lds_bytes = 0;
+    std::map<std::pair<double, int>, std::unique_ptr<Setup>> setups;
+    bool profiling = false;
+    struct Rec { int phase; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+};
+
+struct cyl_heat_s {
+    cyl_plan_t plan = nullptr;
+    std::unique_ptr<Setup> setup;
+    double alpha = 0, dt = 0, kappa = 0;
+    int order = 1;
+    double beta[4] = {0, 0, 0, 0};
+    DevMem P[4], Econst, Xt, lift, T0;
+    bool has_lift = false;
+    int head = 0;          // index of the newest history level
+    long long steps = 0;
+};
+
+namespace cyl {
+namespace {
+
+// ---------------------------------------------------------------------------
+// profiling scopes
+// ---------------------------------------------------------------------------
+struct Scope {
+    cyl_plan_t pl;
+    int phase;
+    hipEvent_t a = nullptr, b = nullptr;
+    Scope(cyl_plan_t p, int ph) : pl(p), phase(ph) {
+        if (!pl->profiling) return;
+        hip_check(hipEventCreate(&a), "hipEventCreate");
+        hip_check(hipEventCreate(&b), "hipEventCreate");
+        hip_check(hipEventRecord(a, pl->stream), "hipEventRecord");
+    }
+    ~Scope() {
+        if (!pl->profiling || !a) return;
+        if (hipEventRecord(b, pl->stream) == hipSuccess) pl->recs.push_back({phase, a, b});
+    }
+};
+
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::atoi(v);
+}
+
+// Passes and per-pass tolerance: for large grids a tight tolerance is reached
+// in two passes of sqrt(eps), with the FP64 residual in between, because one
+// long pass stalls at the rounding floor of the shifted solves.
+void pass_policy(int m, int n, double eps, int* passes, double* eps_pass) {
+    int ps = (eps < 1e-8 && std::max(m, n) >= 192) ? 2 : 1;
+    const int forced = env_int("CYLSPEC_PASSES", 0);
+    if (forced == 1 || forced == 2) ps = forced;
+    *passes = ps;
+    *eps_pass = ps == 2 ? std::sqrt(eps) : eps;
+}
+
+std::unique_ptr<Setup> make_setup(cyl_plan_t pl, double ka, double eps) {
+    auto s = std::make_unique<Setup>();
+    double eps_pass;
+    pass_policy(pl->m, pl->n, eps, &s->passes, &eps_pass);
+    s->h = build_adi_setup(pl->geo, pl->rops, pl->zops, ka, eps_pass);
+    const Geometry& g = pl->geo;
+    const int me0 = g.me[0], me1 = g.me[1], ne0 = g.ne[0], ne1 = g.ne[1];
+    const int64_t blk_off[4] = {0, static_cast<int64_t>(me0) * ne0,
+                                static_cast<int64_t>(me0) * ne0 + static_cast<int64_t>(me0) * ne1,
+                                static_cast<int64_t>(me0) * (ne0 + ne1) + static_cast<int64_t>(me1) * ne0};
+    for (int pl_i = 0; pl_i < g.nplanes; ++pl_i) {
+        const int w = g.plane_w[pl_i];
+        for (int pr = 0; pr < 2; ++pr)
+            for (int pz = 0; pz < 2; ++pz) {
+                BlockDesc b{};
+                b.w = w; b.J = s->h.J[w]; b.me = g.me[pr]; b.ne = g.ne[pz];
+                b.pr = pr; b.pz = pz; b.part = g.plane_part[pl_i]; b.plane = pl_i;
+                b.eoff = pl_i * g.plane_elems + blk_off[2 * pr + pz];
+                b.rstride = static_cast<int64_t>(me0 + me1) * kRRec;
+                b.zstride = static_cast<int64_t>(ne0 + ne1) * kZRec;
+                b.rbase = s->h.roff[w] + (pr ? static_cast<int64_t>(me0) * kRRec : 0);
+                b.zbase = s->h.zoff[w] + (pz ? static_cast<int64_t>(ne0) * kZRec : 0);
+                b.soff = s->h.soff[w];
+                s->hblocks.push_back(b);
+            }
+    }
+    upload(s->rtab, s->h.rtab);
+    upload(s->ztab, s->h.ztab);
+    upload(s->vmu, s->h.vmu);
+    upload(s->blocks, s->hblocks);
+    // operator-apply records of the pencil (residuals): per w, per r parity,
+    // A row then C row at offsets -2..3
+    std::vector<double> at(static_cast<size_t>(g.nw) * (me0 + me1) * 12, 0.0);
+    for (int w = 0; w < g.nw; ++w) {
+        const Band Aw = band_axpby(1.0, pl->rops.A0, -static_cast<double>(w) * w, pl->rops.Cc);
+        const Band A = ka > 0.0 ? band_axpby(1.0, pl->rops.R2Q, -ka, Aw) : Aw;
+        const Band C = ka > 0.0 ? band_axpby(-ka, pl->rops.R2Q, 0.0, pl->rops.R2Q) : pl->rops.R2Q;
+        size_t base = static_cast<size_t>(w) * (me0 + me1) * 12;
+        for (int pr = 0; pr < 2; ++pr) {
+            const Band Ap = band_parity(A, pr), Cp = band_parity(C, pr);
+            for (int i = 0; i < Ap.rows; ++i) {
+                for (int t = 0; t < 6; ++t) {
+                    at[base + i * 12 + t] = Ap.get(i, i - 2 + t);
+                    at[base + i * 12 + 6 + t] = Cp.get(i, i - 2 + t);
+                }
+            }
+            base += static_cast<size_t>(Ap.rows) * 12;
+        }
+    }
+    upload(s->atab, at);
+    return s;
+}
+
+Setup* poisson_setup(cyl_plan_t pl, double eps) {
+    const auto key = std::make_pair(eps, env_int("CYLSPEC_PASSES", 0));
+    auto it = pl->setups.find(key);
+    if (it != pl->setups.end()) return it->second.get();
+    auto s = make_setup(pl, 0.0, eps);
+    Setup* raw = s.get();
+    pl->setups[key] = std::move(s);
+    return raw;
+}
+
+// ---------------------------------------------------------------------------
+// transform sequences
+// ---------------------------------------------------------------------------
+LineSet r_lines(const Geometry& g) {
+    LineSet ls{};
+    ls.outer = static_cast<int64_t>(g.n) * g.m; ls.inner = g.m; ls.elem = 1;
+    ls.n_outer = g.nw; ls.n_inner = g.n;
+    return ls;
+}
+LineSet z_lines(const Geometry& g) {
+    LineSet ls{};
+    ls.outer = static_cast<int64_t>(g.n) * g.m; ls.inner = 1; ls.elem = g.m;
+    ls.n_outer = g.nw; ls.n_inner = g.m;
+    return ls;
+}
+
+void transform_fwd(cyl_plan_t pl, const double* values, double2* coeffs) {
+    Scope sc(pl, PH_FWD);
+    const Geometry& g = pl->geo;
+    hip_check(launch_theta_fwd(values, coeffs, g.m, g.n, g.p, pl->dth.view, pl->stream), "theta_fwd");
+    hip_check(launch_dct(coeffs, coeffs, z_lines(g), g.n, false, pl->dz.view, pl->pre_fz.as<double>(),
+                         pl->post_fz.as<double>(), pl->stream), "dct_z_fwd");
+    hip_check(launch_dct(coeffs, coeffs, r_lines(g), g.m, true, pl->dr.view, pl->pre_fr.as<double>(),
+                         pl->post_fr.as<double>(), pl->stream), "dct_r_fwd");
+}
+
+// coeffs may equal the plan's planesA (in place); coeffs is not modified otherwise.
+void transform_inv(cyl_plan_t pl, const double2* coeffs, double* values) {
+    Scope sc(pl, PH_INV);
+    const Geometry& g = pl->geo;
+    double2* W = pl->planesA.as<double2>();
+    hip_check(launch_dct(coeffs, W, r_lines(g), g.m, true, pl->dr.view, pl->pre_ir.as<double>(),
+                         pl->post_ir.as<double>(), pl->stream), "dct_r_inv");
+    hip_check(launch_dct(W, W, z_lines(g), g.n, false, pl->dz.view, pl->pre_iz.as<double>(),
+                         pl->post_iz.as<double>(), pl->stream), "dct_z_inv");
+    hip_check(launch_theta_inv(W, values, g.m, g.n, g.p, pl->dth.view, pl->stream), "theta_inv");
+}
+
+// ADI solve of all blocks: X <- solution of A X B + C X D = E (setup pencil).
+void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X) {
+    const Geometry& g = pl->geo;
+    const int nblk = static_cast<int>(s->hblocks.size());
+    const int max_elems = g.me[0] * g.ne[0];
+    for (int pass = 0; pass < s->passes; ++pass) {
+        const double* rhs = E;
+        if (pass > 0) {
+            Scope sc(pl, PH_RES);
+            hip_check(launch_apply2(s->blocks.as<BlockDesc>(), nblk, max_elems, E, 1.0, X, 1.0, 1.0,
+                                    pl->R.as<double>(), s->atab.as<double>(),
+                                    static_cast<int64_t>(g.me[0] + g.me[1]) * 12, g.me[0],
+                                    pl->ztabA.as<double>(), g.ne[0], pl->stream), "residual");
+            rhs = pl->R.as<double>();
+        }
+        Scope sc(pl, PH_ADI);
+        hip_check(launch_adi(s->blocks.as<BlockDesc>(), nblk, pl->adi_threads, rhs, X,
+                             pl->state.as<double>(), s->rtab.as<double>(), s->ztab.as<double>(),
+                             s->vmu.as<double>(), pass > 0, pl->use_lds, pl->lds_bytes, pl->stream),
+                  "adi");
+    }
+}
+
+void check_residual(cyl_plan_t pl, Setup* s, const double* E, const double* X, double eps,
+                    cyl_solve_info* info) {
+    const Geometry& g = pl->geo;
+    const int nblk = static_cast<int>(s->hblocks.size());
+    {
+        Scope sc(pl, PH_RES);
+        hip_check(launch_apply2(s->blocks.as<BlockDesc>(), nblk, g.me[0] * g.ne[0], E, 1.0, X, 1.0, 1.0,
+                                pl->R.as<double>(), s->atab.as<double>(),
+                                static_cast<int64_t>(g.me[0] + g.me[1]) * 12, g.me[0],
+                                pl->ztabA.as<double>(), g.ne[0], pl->stream), "residual");
+    }
+    hip_check(hipMemsetAsync(pl->acc.p, 0, 3 * sizeof(double), pl->stream), "memset");
+    hip_check(launch_norms(pl->R.as<double>(), E, X, g.total_elems, pl->acc.as<double>(), pl->stream), "norms");
+    double h[3];
+    hip_check(hipMemcpyAsync(h, pl->acc.p, sizeof(h), hipMemcpyDeviceToHost, pl->stream), "copy norms");
+    hip_check(hipStreamSynchronize(pl->stream), "sync");
+    info->J_max = s->h.J_max;
+    info->J_min = s->h.J_min;
+    info->passes = s->passes;
+    info->reserved = 0;
+    info->adi_iterations_mean = s->h.J_mean;
+    info->resid_ratio = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+    const double lim = 1e3 * std::max(eps, 1e-12);
+    if (h[2] > 0.0 || !std::isfinite(info->resid_ratio) || info->resid_ratio > lim)
+        fail(CYL_E_NOT_CONVERGED, "ADI result not finite or residual ratio " +
+                                      std::to_string(info->resid_ratio) + " above " + std::to_string(lim));
+}
+
+void validate_tol(double eps) {
+    if (!(eps >= 1e-15 && eps <= 1e-2)) fail(CYL_E_INVALID_ARG, "adi_tol must lie in [1e-15, 1e-2]");
+}
+void validate_space(int space) {
+    if (space != CYL_SPACE_VALUE && space != CYL_SPACE_COEFF) fail(CYL_E_INVALID_ARG, "space must be CYL_SPACE_VALUE or CYL_SPACE_COEFF");
+}
+
+void build_plan(cyl_plan_t pl) {
+    const int m = pl->m, n = pl->n, p = pl->p;
+    pl->geo = make_geometry(m, n, p);
+    pl->rops = build_dir_ops(m);
+    pl->zops = build_dir_ops(n);
+    pl->dr.build(2 * (m - 1));
+    pl->dz.build(2 * (n - 1));
+    pl->dth.build(p);
+    // DCT pre/post factors: forward c_k = (-1)^k s_k / M * DCT-I(f)_k with
+    // s_0 = s_M = 1/2; inverse f = DCT-I(g), g_k = (-1)^k c_k (halved inside).
+    auto dct_tabs = [](int len, DevMem& pf, DevMem& qf, DevMem& pi, DevMem& qi) {
+        const int M = len - 1;
+        std::vector<double> pre_f(len, 1.0), post_f(len), pre_i(len), post_i(len, 1.0);
+        for (int k = 0; k < len; ++k) {
+            const double sg = (k & 1) ? -1.0 : 1.0;
+            const double half = (k == 0 || k == M) ? 0.5 : 1.0;
+            post_f[k] = sg * half / M;
+            pre_i[k] = sg * ((k == 0 || k == M) ? 1.0 : 0.5);
+        }
+        upload(pf, pre_f); upload(qf, post_f); upload(pi, pre_i); upload(qi, post_i);
+    };
+    dct_tabs(m, pl->pre_fr, pl->post_fr, pl->pre_ir, pl->post_ir);
+    dct_tabs(n, pl->pre_fz, pl->post_fz, pl->pre_iz, pl->post_iz);
+    // tau right-hand-side tables (full T-coefficient operators)
+    std::vector<double> r2(static_cast<size_t>(m - 2) * 5), a0(static_cast<size_t>(m - 2) * 4),
+        s10(static_cast<size_t>(m - 2) * 4), c02(static_cast<size_t>(n - 2) * 3), d2(n - 2);
+    for (int i = 0; i < m - 2; ++i) {
+        for (int t = 0; t < 5; ++t) r2[i * 5 + t] = pl->rops.R2f.get(i, i - 2 + 2 * t);
+        for (int t = 0; t < 4; ++t) {
+            a0[i * 4 + t] = pl->rops.A0f.get(i, i - 2 + 2 * t);
+            s10[i * 4 + t] = pl->rops.S10f.get(i, i - 2 + 2 * t);
+        }
+    }
+    for (int k = 0; k < n - 2; ++k) {
+        for (int t = 0; t < 3; ++t) c02[k * 3 + t] = pl->zops.C02f.get(k, k + 2 * t);
+        d2[k] = pl->zops.D2f.get(k, k + 2);
+    }
+    upload(pl->t_r2, r2); upload(pl->t_a0, a0); upload(pl->t_s10, s10);
+    upload(pl->t_c02, c02); upload(pl->t_d2, d2);
+    pl->rhs.r2 = pl->t_r2.as<double>(); pl->rhs.a0 = pl->t_a0.as<double>();
+    pl->rhs.s10 = pl->t_s10.as<double>(); pl->rhs.c02 = pl->t_c02.as<double>();
+    pl->rhs.d2 = pl->t_d2.as<double>();
+    const Geometry& g = pl->geo;
+    std::vector<int> pof(2 * g.nw, -1);
+    for (int i = 0; i < g.nplanes; ++i) pof[2 * g.plane_w[i] + g.plane_part[i]] = i;
+    upload(pl->plane_of, pof);
+    // z apply records: B column k at rows k-1..k+2, D column likewise
+    const Band Bt = band_transpose(pl->zops.C02Q), Dt = band_transpose(pl->zops.D2Q);
+    std::vector<double> za(static_cast<size_t>(g.ne[0] + g.ne[1]) * 8, 0.0);
+    size_t base = 0;
+    for (int pz = 0; pz < 2; ++pz) {
+        const Band Bp = band_parity(Bt, pz), Dp = band_parity(Dt, pz);
+        for (int k = 0; k < Bp.cols; ++k)
+            for (int t = 0; t < 4; ++t) {
+                za[base + k * 8 + t] = Bp.get(k - 1 + t, k);
+                za[base + k * 8 + 4 + t] = Dp.get(k - 1 + t, k);
+            }
+        base += static_cast<size_t>(Bp.cols) * 8;
+    }
+    upload(pl->ztabA, za);
+    // projection records (heat history): A = R2 Q rows, C = 0, shared by all w
+    std::vector<double> ap(static_cast<size_t>(g.me[0] + g.me[1]) * 12, 0.0);
+    base = 0;
+    for (int pr = 0; pr < 2; ++pr) {
+        const Band Cp = band_parity(pl->rops.R2Q, pr);
+        for (int i = 0; i < Cp.rows; ++i)
+            for (int t = 0; t < 6; ++t) ap[base + i * 12 + t] = Cp.get(i, i - 2 + t);
+        base += static_cast<size_t>(Cp.rows) * 12;
+    }
+    upload(pl->atab_proj, ap);
+    // workspace
+    const size_t planes_bytes = static_cast<size_t>(g.nw) * n * m * sizeof(double2);
+    const size_t blk_bytes = static_cast<size_t>(g.total_elems) * sizeof(double);
+    pl->planesA.alloc(planes_bytes);
+    pl->planesB.alloc(planes_bytes);
+    pl->E.alloc(blk_bytes);
+    pl->X.alloc(blk_bytes);
+    pl->R.alloc(blk_bytes);
+    pl->acc.alloc(4 * sizeof(double));
+    // ADI variant: LDS-resident when the largest block and its records fit
+    pl->adi_threads = ((std::max(g.me[0], g.ne[0]) + 63) / 64) * 64;
+    pl->lds_bytes = (static_cast<size_t>(g.me[0]) * (g.ne[0] | 1) + static_cast<size_t>(kRRec) * g.me[0] +
+                     static_cast<size_t>(kZRec) * g.ne[0]) * sizeof(double);
+    int dev = 0, max_lds = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 65536;
+    int max_lds_sm = 0;
+    if (hipDeviceGetAttribute(&max_lds_sm, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess)
+        max_lds = std::max(max_lds, max_lds_sm);
+    const int mode = env_int("CYLSPEC_ADI_GLOBAL", 0);
+    pl->use_lds = mode == 0 && pl->adi_threads <= 256 && pl->lds_bytes <= static_cast<size_t>(max_lds);
+    if (pl->use_lds && pl->lds_bytes > 65536) {
+        if (adi_set_lds_limit(pl->lds_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            pl->use_lds = false;
+        }
+    }
+    if (!pl->use_lds) {
+        pl->adi_threads = std::min(1024, pl->adi_threads);
+        pl->state.alloc(blk_bytes);
+    }
+    if (env_int("CYLSPEC_LOG", 0) > 0)
+        std::fprintf(stderr, "[cylspec] plan %dx%dx%d: blocks me=(%d,%d) ne=(%d,%d), ADI %s, %d threads, "
+                             "LDS %zu of %d bytes, DFT Nb r/z/theta = %d/%d/%d\n",
+                     m, n, p, g.me[0], g.me[1], g.ne[0], g.ne[1], pl->use_lds ? "LDS-resident" : "HBM-resident",
+                     pl->adi_threads, pl->lds_bytes, max_lds, pl->dr.t.Nb, pl->dz.t.Nb, pl->dth.t.Nb);
+}
+
+}  // namespace
+}  // namespace cyl
+
+// =============================================================================
+// C ABI
+// =============================================================================
+extern "C" {
+
+const char* cyl_status_string(int status) {
+    switch (status) {
+        case CYL_OK: return "ok";
+        case CYL_E_INVALID_ARG: return "invalid argument";
+        case CYL_E_UNSUPPORTED: return "unsupported size or option";
+        case CYL_E_OUT_OF_MEMORY: return "out of memory";
+        case CYL_E_HIP: return "HIP runtime error";
+        case CYL_E_NOT_CONVERGED: return "ADI did not converge";
+        case CYL_E_INTERNAL: return "internal error";
+        default: return "unknown status";
+    }
+}
+
+const char* cyl_last_error(void) { return g_last_error.c_str(); }
+
+int cyl_plan_create(cyl_plan_t* plan, int n_r, int n_z, int n_theta, void* hip_stream) {
+    return guarded([&] {
+        if (!plan) fail(CYL_E_INVALID_ARG, "plan pointer is NULL");
+        *plan = nullptr;
+        if (n_r < 4 || n_z < 4 || n_theta < 1) fail(CYL_E_INVALID_ARG, "need n_r >= 4, n_z >= 4, n_theta >= 1");
+        if (n_r > 1025 || n_z > 1025 || n_theta > 4096) fail(CYL_E_UNSUPPORTED, "need n_r, n_z <= 1025 and n_theta <= 4096");
+        auto nb_of = [](int L) { if ((L & (L - 1)) == 0) return L; int N = 1; while (N < 2 * L - 1) N <<= 1; return N; };
+        if (nb_of(n_theta) > 4096) fail(CYL_E_UNSUPPORTED, "n_theta that is not a power of two must be <= 2048");
+        auto pl = std::make_unique<cyl_plan_s>();
+        pl->m = n_r; pl->n = n_z; pl->p = n_theta;
+        pl->stream = static_cast<hipStream_t>(hip_stream);
+        build_plan(pl.get());
+        *plan = pl.release();
+    });
+}
+
+int cyl_plan_destroy(cyl_plan_t plan) {
+    return guarded([&] {
+        if (!plan) fail(CYL_E_INVALID_ARG, "plan is NULL");
+        (void)hipStreamSynchronize(plan->stream);
+        for (auto& r : plan->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        delete plan;
+    });
+}
+
+int cyl_transform_fwd(cyl_plan_t plan, const double* values, double* coeffs) {
+    return guarded([&] {
+        if (!plan || !values || !coeffs) fail(CYL_E_INVALID_ARG, "NULL argument");
+        transform_fwd(plan, values, reinterpret_cast<double2*>(coeffs));
+    });
+}
+
+int cyl_transform_inv(cyl_plan_t plan, const double* coeffs, double* values) {
+    return guarded([&] {
+        if (!plan || !values || !coeffs) fail(CYL_E_INVALID_ARG, "NULL argument");
+        transform_inv(plan, reinterpret_cast<const double2*>(coeffs), values);
+    });
+}
+
+int cyl_poisson_solve(cyl_plan_t plan, int space, const double* f, const double* bc_lift, double* u,
+                      double adi_tol, cyl_solve_info* info) {
+    return guarded([&] {
+        if (!plan || !f || !u) fail(CYL_E_INVALID_ARG, "NULL argument");
+        validate_space(space);
+        validate_tol(adi_tol);
+        cyl_plan_s* pl = plan;
+        const Geometry& g = pl->geo;
+        Setup* s = poisson_setup(pl, adi_tol);
+        const double2* F = reinterpret_cast<const double2*>(f);
+        const double2* Lc = reinterpret_cast<const double2*>(bc_lift);
+        if (space == CYL_SPACE_VALUE) {
+            transform_fwd(pl, f, pl->planesA.as<double2>());
+            F = pl->planesA.as<double2>();
+            if (bc_lift) {
+                transform_fwd(pl, bc_lift, pl->planesB.as<double2>());
+                Lc = pl->planesB.as<double2>();
+            }
+        }
+        {
+            Scope sc(pl, PH_RHS);
+            hip_check(launch_rhs3(F, Lc, 1.0, 0.0, -1.0, pl->E.as<double>(), s->blocks.as<BlockDesc>(),
+                                  g.nplanes, g.m, g.n, pl->rhs, pl->stream), "rhs");
+        }
+        adi_solve(pl, s, pl->E.as<double>(), pl->X.as<double>());
+        if (info) check_residual(pl, s, pl->E.as<double>(), pl->X.as<double>(), adi_tol, info);
+        double2* out = space == CYL_SPACE_COEFF ? reinterpret_cast<double2*>(u) : pl->planesA.as<double2>();
+        {
+            Scope sc(pl, PH_REC);
+            hip_check(launch_recombine(pl->X.as<double>(), Lc, out, pl->plane_of.as<int>(),
+                                       s->blocks.as<BlockDesc>(), g.nw, g.m, g.n, g.p, pl->stream), "recombine");
+        }
+        if (space == CYL_SPACE_VALUE) transform_inv(pl, pl->planesA.as<double2>(), u);
+    });
+}
+
+int cyl_heat_create(cyl_heat_t* h, cyl_plan_t plan, double alpha, double dt, int bdf_order,
+                    double adi_tol, int space, const double* const* history, const double* g,
+                    const double* bc_lift) {
+    return guarded([&] {
+        if (!h) fail(CYL_E_INVALID_ARG, "heat handle pointer is NULL");
+        *h = nullptr;
+        if (!plan || !history || !g) fail(CYL_E_INVALID_ARG, "NULL argument");
+        if (!(alpha > 0.0) || !std::isfinite(alpha)) fail(CYL_E_INVALID_ARG, "alpha must be > 0");
+        if (!(dt > 0.0) || !std::isfinite(dt)) fail(CYL_E_INVALID_ARG, "dt must be > 0");
+        if (bdf_order != 1 && bdf_order != 4) fail(CYL_E_UNSUPPORTED, "bdf_order must be 1 or 4");
+        validate_space(space);
+        validate_tol(adi_tol);
+        for (int i = 0; i < bdf_order; ++i)
+            if (!history[i]) fail(CYL_E_INVALID_ARG, "NULL history level");
+        cyl_plan_s* pl = plan;
+        const Geometry& geo = pl->geo;
+        auto H = std::make_unique<cyl_heat_s>();
+        H->plan = pl;
+        H->alpha = alpha; H->dt = dt; H->order = bdf_order;
+        if (bdf_order == 1) { H->kappa = dt; H->beta[0] = 1.0; }
+        else {
+            H->kappa = 12.0 * dt / 25.0;
+            H->beta[0] = 48.0 / 25.0; H->beta[1] = -36.0 / 25.0; H->beta[2] = 16.0 / 25.0; H->beta[3] = -3.0 / 25.0;
+        }
+        const double ka = H->kappa * alpha;
+        H->setup = make_setup(pl, ka, adi_tol);
+        const size_t blk_bytes = static_cast<size_t>(geo.total_elems) * sizeof(double);
+        const size_t planes_bytes = static_cast<size_t>(geo.nw) * geo.n * geo.m * sizeof(double2);
+        for (int i = 0; i < bdf_order; ++i) H->P[i].alloc(blk_bytes);
+        H->Econst.alloc(blk_bytes);
+        H->Xt.alloc(blk_bytes);
+        H->T0.alloc(planes_bytes);
+        const BlockDesc* blocks = H->setup->blocks.as<BlockDesc>();
+        const double2* Lc = nullptr;
+        if (bc_lift) {
+            H->lift.alloc(planes_bytes);
+            H->has_lift = true;
+            if (space == CYL_SPACE_VALUE) transform_fwd(pl, bc_lift, H->lift.as<double2>());
+            else hip_check(hipMemcpyAsync(H->lift.p, bc_lift, planes_bytes, hipMemcpyDeviceToDevice, pl->stream), "copy lift");
+            Lc = H->lift.as<double2>();
+        }
+        // history levels -> P_i = [R2 (T_i - L) C02^T]_tau
+        for (int i = 0; i < bdf_order; ++i) {
+            const double2* C;
+            if (space == CYL_SPACE_VALUE) {
+                double2* dst = (i == 0) ? H->T0.as<double2>() : pl->planesA.as<double2>();
+                transform_fwd(pl, history[i], dst);
+                C = dst;
+            } else {
+                if (i == 0) hip_check(hipMemcpyAsync(H->T0.p, history[0], planes_bytes, hipMemcpyDeviceToDevice, pl->stream), "copy T0");
+                C = reinterpret_cast<const double2*>(history[i]);
+            }
+            Scope sc(pl, PH_RHS);
+            hip_check(launch_rhs3(C, Lc, 1.0, -1.0, 0.0, H->P[i].as<double>(), blocks, geo.nplanes, geo.m,
+                                  geo.n, pl->rhs, pl->stream), "history rhs");
+        }
+        // constant part: kappa [R2 G C02^T]_tau + kappa alpha [r^2 nabla^2 L]_tau
+        const double2* G;
+        if (space == CYL_SPACE_VALUE) {
+            transform_fwd(pl, g, pl->planesA.as<double2>());
+            G = pl->planesA.as<double2>();
+        } else {
+            G = reinterpret_cast<const double2*>(g);
+        }
+        {
+            Scope sc(pl, PH_RHS);
+            hip_check(launch_rhs3(G, Lc, H->kappa, 0.0, ka, H->Econst.as<double>(), blocks, geo.nplanes,
+                                  geo.m, geo.n, pl->rhs, pl->stream), "forcing rhs");
+        }
+        H->head = 0;
+        *h = H.release();
+    });
+}
+
+int cyl_heat_step(cyl_heat_t h, int n_steps) {
+    return guarded([&] {
+        if (!h) fail(CYL_E_INVALID_ARG, "heat handle is NULL");
+        if (n_steps < 0) fail(CYL_E_INVALID_ARG, "n_steps must be >= 0");
+        cyl_plan_s* pl = h->plan;
+        const Geometry& g = pl->geo;
+        Setup* s = h->setup.get();
+        const int nblk = static_cast<int>(s->hblocks.size());
+        for (int st = 0; st < n_steps; ++st) {
+            const double* P[4];
+            for (int i = 0; i < h->order; ++i) P[i] = h->P[(h->head + i) % h->order].as<double>();
+            {
+                Scope sc(pl, PH_HRHS);
+                hip_check(launch_heat_rhs(pl->E.as<double>(), P, h->beta, h->order, h->Econst.as<double>(),
+                                          g.total_elems, pl->stream), "heat rhs");
+            }
+            adi_solve(pl, s, pl->E.as<double>(), h->Xt.as<double>());
+            // the oldest slot becomes the newest: P_new = C~ Xt B~
+            const int slot = (h->head + h->order - 1) % h->order;
+            {
+                Scope sc(pl, PH_PROJ);
+                hip_check(launch_apply2(s->blocks.as<BlockDesc>(), nblk, g.me[0] * g.ne[0], nullptr, 0.0,
+                                        h->Xt.as<double>(), -1.0, 0.0, h->P[slot].as<double>(),
+                                        pl->atab_proj.as<double>(), 0, g.me[0], pl->ztabA.as<double>(),
+                                        g.ne[0], pl->stream), "project");
+            }
+            h->head = slot;
+            ++h->steps;
+        }
+    });
+}
+
+int cyl_heat_read(cyl_heat_t h, int space, double* T_out) {
+    return guarded([&] {
+        if (!h || !T_out) fail(CYL_E_INVALID_ARG, "NULL argument");
+        validate_space(space);
+        cyl_plan_s* pl = h->plan;
+        const Geometry& g = pl->geo;
+        const size_t planes_bytes = static_cast<size_t>(g.nw) * g.n * g.m * sizeof(double2);
+        if (h->steps == 0) {
+            if (space == CYL_SPACE_COEFF)
+                hip_check(hipMemcpyAsync(T_out, h->T0.p, planes_bytes, hipMemcpyDeviceToDevice, pl->stream), "copy");
+            else
+                transform_inv(pl, h->T0.as<double2>(), T_out);
+            return;
+        }
+        double2* out = space == CYL_SPACE_COEFF ? reinterpret_cast<double2*>(T_out) : pl->planesA.as<double2>();
+        {
+            Scope sc(pl, PH_REC);
+            hip_check(launch_recombine(h->Xt.as<double>(), h->has_lift ? h->lift.as<double2>() : nullptr, out,
+                                       pl->plane_of.as<int>(), h->setup->blocks.as<BlockDesc>(), g.nw, g.m, g.n,
+                                       g.p, pl->stream), "recombine");
+        }
+        if (space == CYL_SPACE_VALUE) transform_inv(pl, pl->planesA.as<double2>(), T_out);
+    });
+}
+
+int cyl_heat_destroy(cyl_heat_t h) {
+    return guarded([&] {
+        if (!h) fail(CYL_E_INVALID_ARG, "heat handle is NULL");
+        (void)hipStreamSynchronize(h->plan->stream);
+        delete h;
+    });
+}
+
+int cyl_adi_parameters(int n_r, int n_z, int w, double kappa_alpha, double adi_tol, double* bounds4,
+                       int* J, double* u, double* v, int cap) {
+    return guarded([&] {
+        if (n_r < 4 || n_z < 4 || w < 0 || kappa_alpha < 0.0 || !bounds4 || !J)
+            fail(CYL_E_INVALID_ARG, "invalid argument");
+        if (n_r > 1025 || n_z > 1025) fail(CYL_E_UNSUPPORTED, "n_r, n_z <= 1025");
+        validate_tol(adi_tol);
+        const DirOps r = build_dir_ops(n_r), z = build_dir_ops(n_z);
+        double zc, zd;
+        pencil_bounds_z(band_transpose(z.C02Q), band_transpose(z.D2Q), &zc, &zd);
+        std::vector<double> uu, vv;
+        mode_parameters(r, z, w, kappa_alpha, adi_tol, zc, zd, bounds4, J, &uu, &vv);
+        if (u && v) {
+            if (cap < *J) fail(CYL_E_INVALID_ARG, "shift capacity smaller than J");
+            std::copy(uu.begin(), uu.end(), u);
+            std::copy(vv.begin(), vv.end(), v);
+        }
+    });
+}
+
+int cyl_plan_set_profiling(cyl_plan_t plan, int enable) {
+    return guarded([&] {
+        if (!plan) fail(CYL_E_INVALID_ARG, "plan is NULL");
+        plan->profiling = enable != 0;
+    });
+}
+
+int cyl_plan_get_profile(cyl_plan_t plan, cyl_profile* out) {
+    return guarded([&] {
+        if (!plan || !out) fail(CYL_E_INVALID_ARG, "NULL argument");
+        hip_check(hipStreamSynchronize(plan->stream), "sync");
+        double ms[PH_COUNT] = {0};
+        int cnt[PH_COUNT] = {0};
+        for (auto& r : plan->recs) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) { ms[r.phase] += t; cnt[r.phase] += 1; }
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        plan->recs.clear();
+        out->ms_transform_fwd = ms[PH_FWD]; out->n_transform_fwd = cnt[PH_FWD];
+        out->ms_rhs = ms[PH_RHS]; out->n_rhs = cnt[PH_RHS];
+        out->ms_adi = ms[PH_ADI]; out->n_adi = cnt[PH_ADI];
+        out->ms_residual = ms[PH_RES]; out->n_residual = cnt[PH_RES];
+        out->ms_recombine = ms[PH_REC]; out->n_recombine = cnt[PH_REC];
+        out->ms_transform_inv = ms[PH_INV]; out->n_transform_inv = cnt[PH_INV];
+        out->ms_heat_rhs = ms[PH_HRHS]; out->n_heat_rhs = cnt[PH_HRHS];
+        out->ms_project = ms[PH_PROJ]; out->n_project = cnt[PH_PROJ];
+    });
+}
+
+}  // extern "C"

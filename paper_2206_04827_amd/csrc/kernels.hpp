@@ -1,0 +1,89 @@
+// Launchers of the device kernels (plain pointers; called from the C API).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace cyl {
+
+// Device view of one DFT length (see DftTables): complex length L computed as
+// a power-of-two FFT of length Nb, directly (L == Nb) or by Bluestein.
+struct DftDev {
+    int L, Nb, log2Nb, bluestein;
+    const double2* tw;      // Nb twiddles exp(-2 pi i k / Nb)
+    const double2* chirp;   // L   (Bluestein only)
+    const double2* bhat;    // Nb  (Bluestein only)
+};
+
+// A family of equally strided lines: line = (o, i), o < n_outer, i < n_inner;
+// element e of a line sits at o * outer + i * inner + e * elem (in double2).
+struct LineSet {
+    int64_t outer, inner, elem;
+    int n_outer, n_inner;
+};
+
+// One ADI work item: a parity block (w, part, pr, pz) of a real mode plane.
+struct BlockDesc {
+    int w, J, me, ne;
+    int pr, pz, part, plane;
+    int64_t eoff;            // offset of the block in E / X (doubles)
+    int64_t rbase, zbase;    // offset of (j = 0) records in rtab / ztab
+    int64_t rstride, zstride;// record stride between successive shifts
+    int64_t soff;            // offset of v_j - u_j values
+};
+
+// ---- transforms (Section 2) ----
+hipError_t launch_theta_fwd(const double* values, double2* planes, int m, int n, int p,
+                            const DftDev& d, hipStream_t s);
+hipError_t launch_theta_inv(const double2* planes, double* values, int m, int n, int p,
+                            const DftDev& d, hipStream_t s);
+// DCT-I of every line: out_k = post[k] * sum_n pre[n] in_n * w_n cos(pi k n / M)
+// (w_n = 1 at both ends, 2 inside), M = mlen - 1.
+hipError_t launch_dct(const double2* in, double2* out, const LineSet& ls, int mlen,
+                      bool contiguous_lines, const DftDev& d, const double* pre,
+                      const double* post, hipStream_t s);
+
+// ---- right-hand side (tau rows) and recombination ----
+struct RhsTables {
+    const double* r2;    // (m-2) x 5 : R2 row i at columns i-2, i, i+2, i+4, i+6
+    const double* a0;    // (m-2) x 4 : (R C12 D1 + R^2 D2) row i at i-2, i, i+2, i+4
+    const double* s10;   // (m-2) x 4 : C02 row i at i-2, i, i+2, i+4 (first entry 0)
+    const double* c02;   // (n-2) x 3 : C02 row k at k, k+2, k+4
+    const double* d2;    // (n-2)     : D2 row k at k+2
+};
+// E = sF [R2 (F + cL L) C02^T]_tau + sL [A_w L C02^T + R2 L D2^T]_tau (L may be NULL)
+hipError_t launch_rhs3(const double2* F, const double2* L, double sF, double cL, double sL,
+                       double* E, const BlockDesc* blocks, int nplanes, int m, int n,
+                       const RhsTables& t, hipStream_t s);
+hipError_t launch_recombine(const double* X, const double2* L, double2* planes,
+                            const int* block_of_plane, const BlockDesc* blocks, int nw,
+                            int m, int n, int p, hipStream_t s);
+
+// ---- ADI (Algorithm 1) ----
+hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, const double* E,
+                      double* X, double* state, const double* rtab, const double* ztab,
+                      const double* vmu, bool accumulate, bool use_lds, size_t lds_bytes,
+                      hipStream_t s);
+
+// Raise the dynamic-LDS limit of the LDS-resident ADI kernel.
+hipError_t adi_set_lds_limit(size_t bytes);
+
+// out = sE * E - sAB * (A X B) - sCD * (C X D) blockwise.  atab: per (w, r
+// parity) rows of 12 (A row i at i-2..i+3, then C row i at i-2..i+3), w stride
+// a_wstride (0: the same rows for every w); ztabA: per z parity columns of 8
+// (B column k at rows k-1..k+2, then D column k at rows k-1..k+2).
+hipError_t launch_apply2(const BlockDesc* blocks, int nblocks, int max_elems, const double* E,
+                         double sE, const double* X, double sAB, double sCD, double* out,
+                         const double* atab, int64_t a_wstride, int me0, const double* ztabA,
+                         int ne0, hipStream_t s);
+
+// ---- heat ----
+hipError_t launch_heat_rhs(double* E, const double* const* P, const double* beta, int nb,
+                           const double* Econst, int64_t total, hipStream_t s);
+
+// ---- reductions ----
+// acc[0] += sum R^2, acc[1] += sum E^2, acc[2] += count of non-finite X
+hipError_t launch_norms(const double* R, const double* E, const double* X, int64_t total,
+                        double* acc, hipStream_t s);
+
+}  // namespace cyl

@@ -1,0 +1,109 @@
+// Host-side planning for the CCF cylinder solver: banded operators of
+// Section 3, spectral bounds, Zolotarev shifts, per-shift LU tables and the
+// per-length DFT tables used by the transform kernels.  Pure C++; no HIP.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace cyl {
+
+// Rectangular banded matrix: entry (i, j) is stored iff -lo <= j - i <= hi.
+struct Band {
+    int rows = 0, cols = 0, lo = 0, hi = 0;
+    std::vector<double> v;
+    Band() = default;
+    Band(int r, int c, int l, int h);
+    int width() const { return lo + hi + 1; }
+    double get(int i, int j) const;
+    void set(int i, int j, double x);
+};
+
+Band band_mul(const Band& A, const Band& B);
+Band band_axpby(double alpha, const Band& A, double beta, const Band& B);
+Band band_cut(const Band& A, int rows, int cols);
+Band band_transpose(const Band& A);
+// Rows/columns of one index parity (p = 0 even, 1 odd); the operators here
+// never couple the two parities, which is checked.
+Band band_parity(const Band& A, int p);
+
+// Operators of eq. (HelmholtzMatEqn) for one direction of size n.
+struct DirOps {
+    int n = 0;
+    // Dirichlet-basis tau matrices, (n-2) x (n-2), full index (not parity split).
+    Band A0;   // [(R C12 D1 + R^2 D2) Q]_tau           (radial part, w = 0)
+    Band Cc;   // [C02 Q]_tau                            (coefficient of -w^2)
+    Band R2Q;  // [R^2 C02 Q]_tau                        (r-direction C)
+    Band C02Q; // [C02 Q]_tau                            (z-direction B^T)
+    Band D2Q;  // [D2 Q]_tau                             (z-direction D^T)
+    // Full T-coefficient operators, n x n, for right-hand sides and lifts.
+    Band R2f, C02f, A0f, S10f, D2f;
+};
+DirOps build_dir_ops(int n);
+
+// Spectral bounds of Section 3 for the Poisson pencils.
+struct Bounds { double a, b, c, d; };
+// Enclosing [a,b] of C^-1 A_w over both parity blocks, given A_w and C.
+void pencil_bounds_r(const Band& A, const Band& C, double* a, double* b);
+// Enclosing [c,d] of -D B^-1 over both parity blocks, given B = C02Q^T, D = D2Q^T.
+void pencil_bounds_z(const Band& B, const Band& D, double* c, double* d);
+
+// Zolotarev shifts (Section 3): u_j in [c,d] (first half-step), v_j in [a,b].
+int adi_num_iterations(double a, double b, double c, double d, double eps);
+void adi_shifts(double a, double b, double c, double d, int J, double* u, double* v);
+double jacobi_dn_frac(double t, double kp);   // dn(t K(k), k), 0 <= t <= 1
+double ellip_K_from_kp(double kp);
+
+// Per-length DFT tables (complex length L; power-of-two FFT length Nb).
+struct DftTables {
+    int L = 0, Nb = 0, log2Nb = 0;
+    bool bluestein = false;
+    std::vector<double> tw;     // 2*Nb: exp(-2 pi i k / Nb)
+    std::vector<double> chirp;  // 2*L : exp(-i pi n^2 / L)
+    std::vector<double> bhat;   // 2*Nb: FFT of the Bluestein filter, times 1/Nb
+};
+DftTables build_dft_tables(int L);
+
+// Record layouts of the ADI coefficient tables (doubles per row).
+constexpr int kRRec = 12;   // r-pass: (vC - A) row[6], L[2], dinv, dinv*U[3]
+constexpr int kZRec = 8;    // z-pass: L, dinv, dinv*U[2], (u'B + D)^T row[4]
+
+// Pencil + tolerance -> everything the ADI kernels read.
+struct AdiSetup {
+    double kappa_alpha = 0.0, eps = 0.0;
+    int nw = 0;
+    std::vector<int> J;                 // per w slot
+    std::vector<double> bounds;         // 4 per w slot
+    std::vector<int64_t> roff, zoff;    // per w slot: offset of its tables
+    std::vector<double> rtab, ztab;     // coefficient records
+    std::vector<double> vmu;            // per (w, j): v_j - u_j, offset soff[w]
+    std::vector<int64_t> soff;
+    int J_max = 0, J_min = 0;
+    double J_mean = 0.0;
+};
+
+struct Geometry {
+    int m = 0, n = 0, p = 0;    // n_r, n_z, n_theta
+    int nw = 0;                 // floor(p/2) + 1 coefficient slots
+    int me[2] = {0, 0};         // r parity block sizes
+    int ne[2] = {0, 0};         // z parity block sizes
+    int nplanes = 0;            // real mode planes (= p)
+    std::vector<int> plane_w, plane_part;   // per real plane
+    int64_t plane_elems = 0;    // (m-2)(n-2)
+    int64_t total_elems = 0;    // nplanes * plane_elems
+};
+Geometry make_geometry(int m, int n, int p);
+
+// Build the ADI setup for pencil (A_w - kappa_alpha-scaled) and tolerance eps.
+// kappa_alpha == 0: Poisson pencil (A_w, C).  Otherwise the heat pencil
+// (C - ka A_w, -ka C).
+AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z,
+                         double kappa_alpha, double eps);
+
+// Bounds/J/shifts of one wavenumber (shared by the setup and the host query).
+void mode_parameters(const DirOps& r, const DirOps& z, int w, double kappa_alpha,
+                     double eps, double zc, double zd, double* bounds4, int* J,
+                     std::vector<double>* u, std::vector<double>* v);
+
+}  // namespace cyl

@@ -1,0 +1,174 @@
+"""GPU parity of the Poisson solve against the oracle (Sections 2-3).
+
+Full-field comparisons at sizes the oracle finishes in seconds (several
+blocks and ragged parity tails); at the benchmark's 256^3 and at 512^3 the
+GPU runs the full value-space solve and sampled wavenumbers are compared with
+the oracle's per-mode solves.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2206_04827_amd as cyl
+import synth
+from oracle import problems as pb
+from oracle import transforms as tr
+from tests.gpu_common import S, TOL, assert_close, banner, dev, host, need_gpu, smooth_values
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve_values(m, n, p, f, tol=1e-12, lift=None, info=False):
+    plan = cyl.Plan(m, n, p)
+    out = plan.poisson_solve(dev(f), bc_lift=None if lift is None else dev(lift), adi_tol=tol,
+                             info=info)
+    if info:
+        return host(out[0]), out[1]
+    return host(out)
+
+
+def test_p32_config_full_field():
+    """32^3, decaying random CCF forcing (seed S+0), ADI tolerance 1e-12."""
+    need_gpu()
+    banner("poisson P32")
+    m = n = p = 32
+    f = smooth_values(m, n, p, S + 0)
+    u, info = _solve_values(m, n, p, f, 1e-12, info=True)
+    ref = pb.poisson(f)
+    print("  info", info)
+    assert_close(u, ref, TOL, "P32")
+    assert info["resid_ratio"] < 1e-9
+
+
+@pytest.mark.parametrize("m,n,p", [(6, 5, 3), (20, 17, 9), (33, 41, 12), (64, 48, 20), (47, 80, 1)])
+def test_ragged_sizes_full_field(m, n, p):
+    need_gpu()
+    banner("poisson ragged m=%d n=%d p=%d" % (m, n, p))
+    f = smooth_values(m, n, p, S + 100 + m)
+    u = _solve_values(m, n, p, f)
+    assert_close(u, pb.poisson(f), TOL, "ragged")
+
+
+def test_coefficient_space_matches_oracle_coefficients():
+    need_gpu()
+    m, n, p = 24, 20, 10
+    banner("poisson coefficient space")
+    h = synth.smooth_coeffs(m, n, p, S + 7)
+    plan = cyl.Plan(m, n, p)
+    got = host(plan.poisson_solve(dev(h), space=cyl.CYL_SPACE_COEFF))
+    ref = tr.to_half(pb.poisson_coeffs(tr.from_half(h, p)))
+    assert_close(got, ref, TOL, "coeff")
+
+
+def test_manufactured_polynomial_and_lift():
+    """Polynomial solution with nonzero boundary values, lift with the same
+    boundary values but a different interior: exact recovery."""
+    need_gpu()
+    m, n, p = 12, 10, 6
+    r, z, th = tr.grid(m, n, p)
+    TH, Z, R = np.meshgrid(th, z, r, indexing="ij")
+    X, Y = R * np.cos(TH), R * np.sin(TH)
+    u = 1.0 + X + 2 * Y * Z + X * X - Y * Y + 3 * Z ** 3
+    f = 18.0 * Z
+    lift = u + (1 - R ** 2) * (1 - Z ** 2) * (0.3 + X * Z - Y ** 2)
+    got = _solve_values(m, n, p, f, lift=lift)
+    assert np.max(np.abs(got - u)) < 1e-12
+
+
+def test_solution_vanishes_on_boundary_and_is_deterministic():
+    need_gpu()
+    m, n, p = 26, 22, 8
+    f = smooth_values(m, n, p, S + 11)
+    plan = cyl.Plan(m, n, p)
+    fd = dev(f)
+    a = host(plan.poisson_solve(fd))
+    b = host(plan.poisson_solve(fd))
+    assert np.array_equal(a, b)
+    assert np.max(np.abs(a[:, :, 0])) < 1e-14 and np.max(np.abs(a[:, :, -1])) < 1e-14
+    assert np.max(np.abs(a[:, 0, :])) < 1e-14 and np.max(np.abs(a[:, -1, :])) < 1e-14
+
+
+@pytest.mark.parametrize("env", [{"CYLSPEC_ADI_GLOBAL": "1"}, {"CYLSPEC_PASSES": "2"},
+                                 {"CYLSPEC_PASSES": "1"}])
+def test_variants_match(env):
+    """The HBM-resident ADI variant and the one/two-pass policies agree."""
+    need_gpu()
+    m, n, p = 40, 36, 10
+    banner("poisson variant %s" % env)
+    f = smooth_values(m, n, p, S + 21)
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        u = _solve_values(m, n, p, f)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    assert_close(u, pb.poisson(f), TOL, str(env))
+
+
+def test_non_finite_input_reports_not_converged():
+    need_gpu()
+    m, n, p = 10, 10, 4
+    f = smooth_values(m, n, p, S + 3)
+    f[1, 2, 3] = np.nan
+    plan = cyl.Plan(m, n, p)
+    with pytest.raises(cyl.CylError) as e:
+        plan.poisson_solve(dev(f), info=True)
+    assert e.value.status == 5
+
+
+def test_argument_errors_enqueue_nothing():
+    need_gpu()
+    plan = cyl.Plan(8, 8, 4)
+    f = torch.zeros(plan.value_shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(cyl.CylError) as e:
+        plan.poisson_solve(f, adi_tol=0.5)
+    assert e.value.status == 1
+    lib = cyl.load()
+    assert lib.cyl_poisson_solve(plan._h, 7, cyl._ptr(f), None, cyl._ptr(f), 1e-12, None) == 1
+
+
+def _sampled(m, n, p, seed, tol, ls_w):
+    """Value-space GPU solve at full size; sampled wavenumbers vs the oracle."""
+    f = smooth_values(m, n, p, seed)
+    plan = cyl.Plan(m, n, p)
+    fd = dev(f)
+    u = plan.poisson_solve(fd, adi_tol=tol)
+    del fd
+    got_c = tr.forward(host(u))                 # oracle transform of the GPU field
+    del u
+    torch.cuda.empty_cache()
+    cf = tr.forward(f)
+    wn = list(tr.wavenumbers(p))
+    ls = [wn.index(w) for w in ls_w]
+    ref = pb.poisson_coeffs(cf, modes=ls)
+    num = sum(np.linalg.norm(got_c[l] - ref[l]) ** 2 for l in ls) ** 0.5
+    den = sum(np.linalg.norm(ref[l]) ** 2 for l in ls) ** 0.5
+    mx = max(np.max(np.abs(got_c[l] - ref[l])) for l in ls) / max(np.max(np.abs(ref[l])) for l in ls)
+    print("  sampled w=%s rel l2 %.3e rel max %.3e" % (ls_w, num / den, mx), flush=True)
+    for l, w in zip(ls, ls_w):
+        e = np.linalg.norm(got_c[l] - ref[l]) / np.linalg.norm(ref[l])
+        print("    w=%d mode rel %.3e" % (w, e), flush=True)
+    return num / den, mx
+
+
+def test_p256_sampled_modes():
+    """The benchmark configuration: 256^3 value-space solve, eps = 1e-12."""
+    need_gpu()
+    banner("poisson P256 sampled")
+    l2, mx = _sampled(256, 256, 256, S + 3, 1e-12, [0, 1, 2, 3, 64, 127, -128, -5])
+    assert l2 <= TOL and mx <= TOL
+
+
+def test_p512_sampled_modes():
+    """512^3 value-space solve, eps = 1e-10 (largest single solve)."""
+    need_gpu()
+    banner("poisson P512 sampled")
+    l2, mx = _sampled(512, 512, 512, S + 4, 1e-10, [0, 1, 2, 255, -256])
+    assert l2 <= TOL and mx <= TOL

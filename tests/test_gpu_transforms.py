@@ -1,0 +1,48 @@
+"""GPU parity of the value <-> coefficient transforms (Section 2) against the oracle."""
+
+import numpy as np
+import pytest
+
+import paper_2206_04827_amd as cyl
+from oracle import transforms as tr
+from tests.gpu_common import banner, dev, host, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+# power-of-two and Bluestein lengths, odd/even/1/2 theta counts, ragged tails
+SIZES = [(4, 4, 1), (8, 6, 4), (9, 7, 5), (17, 33, 16), (33, 20, 12), (32, 32, 32),
+         (48, 40, 30), (65, 17, 2), (20, 129, 7), (130, 66, 64)]
+
+
+@pytest.mark.parametrize("m,n,p", SIZES)
+def test_forward_and_inverse_match_oracle(m, n, p):
+    need_gpu()
+    banner("transforms m=%d n=%d p=%d" % (m, n, p))
+    f = np.random.default_rng(m * 1000 + n * 10 + p).standard_normal((p, n, m))
+    plan = cyl.Plan(m, n, p)
+    c = host(plan.transform_fwd(dev(f)))
+    ref = tr.to_half(tr.forward(f))
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(c - ref)) / scale
+    print("  fwd rel max %.3e" % err)
+    assert err < 1e-13
+    v = host(plan.transform_inv(dev(ref)))
+    err2 = np.max(np.abs(v - f)) / np.max(np.abs(f))
+    print("  inv rel max %.3e" % err2)
+    assert err2 < 1e-13
+    # the inverse does not modify its input
+    r = dev(ref)
+    plan.transform_inv(r)
+    assert np.array_equal(host(r), ref)
+
+
+def test_inverse_ignores_imaginary_parts_of_real_slots():
+    need_gpu()
+    m, n, p = 10, 8, 6
+    h = np.random.default_rng(0).standard_normal((p // 2 + 1, n, m)) * (1 + 1j)
+    plan = cyl.Plan(m, n, p)
+    v = host(plan.transform_inv(dev(h)))
+    hr = h.copy()
+    hr[0] = hr[0].real
+    hr[p // 2] = hr[p // 2].real
+    assert np.max(np.abs(v - tr.inverse(tr.from_half(hr, p)))) < 1e-13 * np.max(np.abs(v))
