@@ -1,0 +1,164 @@
+"""Benchmark: value-space Poisson solve on the 256^3 CCF grid in FP64.
+
+One step = one whole solve through the hot path: forward transform (theta DFT,
+z and r DCT-I), tau right-hand side, ADI over every parity block of every
+Fourier mode, recombination and inverse transform.  Input: seeded random
+smooth forcing with a decaying CCF spectrum, resident in HBM before timing.
+
+Prints one JSON line.  Besides the headline value it carries:
+  roofline      the ADI kernel's FP64 rate against the vector FP64 peak,
+                from HIP events recorded around every ADI launch on the
+                plan's stream inside the timed region;
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same solve;
+  heat_128      forward BDF1 heat steps per second on the 128^3 grid.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("Poisson unknowns/sec at 256³ FP64 (rel err≤1e-10); "
+          "heat fwd+adjoint steps/sec")
+FP64_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+# FP64 operations per interior unknown per ADI iteration in the kernel's
+# formulation: r-pass 24 (banded product 11, E term 2, forward 4, backward 7),
+# z-pass 14 (forward 2, backward 5, banded product 7).
+ADI_FLOPS_PER_UNKNOWN_ITER = 38.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--tol", type=float, default=1e-12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-heat", action="store_true")
+    ap.add_argument("--cpu-modes", type=int, default=16,
+                    help="wavenumbers the CPU oracle solves in its timed sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(m, n, p, seed, nmodes):
+    """Time the oracle (numpy/scipy, as it stands) on a bounded sample."""
+    import numpy as np
+    import synth
+    from oracle import problems as pb
+    from oracle import transforms as tr
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    h = synth.smooth_coeffs(m, n, p, seed)
+    f = tr.inverse(tr.from_half(h, p))
+    t0 = time.perf_counter()
+    c = tr.forward(f)
+    t_fwd = time.perf_counter() - t0
+    ls = list(range(0, p, max(1, p // nmodes)))[:nmodes]
+    t0 = time.perf_counter()
+    U = pb.poisson_coeffs(c, modes=ls)
+    t_modes = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tr.inverse(U)
+    t_inv = time.perf_counter() - t0
+    t_total = t_fwd + t_inv + t_modes * p / len(ls)
+    return {"value": m * n * p / t_total, "unit": "unknowns/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": ("%d^3 Poisson: forward and inverse transforms of the full field timed, "
+                       "per-mode Bartels-Stewart + 2 extended-precision refinements timed on "
+                       "%d of %d wavenumbers (every %d-th) and scaled to all; %.2f s measured, "
+                       "%.1f s extrapolated") % (m, len(ls), p, max(1, p // nmodes),
+                                                 t_fwd + t_inv + t_modes, t_total)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the path shards by Fourier mode; "
+              "see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2206_04827_amd as cyl
+    import synth
+
+    torch.cuda.set_device(0)
+    m = n = p = args.size
+    plan = cyl.Plan(m, n, p)
+    coeff = torch.from_numpy(synth.smooth_coeffs(m, n, p, synth.SEED_BASE + 3)).cuda()
+    f = plan.transform_inv(coeff)          # forcing values on the grid, resident in HBM
+    u = torch.empty_like(f)
+    # one untimed solve with the residual check (builds the shift tables)
+    _, info = plan.poisson_solve(f, adi_tol=args.tol, out=u, info=True)
+    for _ in range(args.warmup):
+        plan.poisson_solve(f, adi_tol=args.tol, out=u)
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    plan.profile()                         # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.poisson_solve(f, adi_tol=args.tol, out=u)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = plan.profile()
+    plan.set_profiling(False)
+    ms_step = 1e3 * elapsed / args.steps
+    value = m * n * p * args.steps / elapsed
+
+    n_adi = max(1, prof["n_adi"])
+    adi_ms = prof["ms_adi"] / n_adi
+    passes = info["passes"]
+    flops_per_launch = ADI_FLOPS_PER_UNKNOWN_ITER * (m - 2) * (n - 2) * p * info["adi_iterations_mean"]
+    achieved = flops_per_launch / (adi_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "k_adi_lds (one ADI pass over all parity blocks)",
+                "avg_launch_ms": round(adi_ms, 4), "launches": n_adi}
+    phases = {k[3:]: round(prof[k] / args.steps, 4) for k in prof if k.startswith("ms_")}
+
+    out = {"metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "poisson_%d^3_value_space" % m, "n_r": m, "n_z": n, "n_theta": p,
+                      "adi_tol": args.tol, "adi_passes": passes,
+                      "adi_iterations_mean_per_pass": info["adi_iterations_mean"],
+                      "forcing": "seeded decaying random CCF spectrum",
+                      "parallelism": "single GPU"},
+           "resid_ratio": info["resid_ratio"], "phase_ms_per_step": phases,
+           "roofline": roofline}
+
+    if not args.no_heat:
+        hp = cyl.Plan(128, 128, 128)
+        prm = synth.eigenmode_params(synth.SEED_BASE + 1)
+        T0 = torch.from_numpy(synth.eigenmode_values(prm, 128, 128, 128)).cuda()
+        gc = torch.from_numpy(synth.smooth_coeffs(128, 128, 128, synth.SEED_BASE + 2)).cuda()
+        g = hp.transform_inv(gc)
+        H = cyl.Heat(hp, [T0], g, 1.0, 1e-3, 1, 1e-12)
+        H.step(5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H.step(100)
+        torch.cuda.synchronize()
+        th = time.perf_counter() - t0
+        out["heat_128"] = {"steps_per_s": 100 / th, "ms_per_step": 1e3 * th / 100,
+                           "note": "forward BDF1 steps only (no adjoint in this build)"}
+        H.close()
+        hp.close()
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(m, n, p, synth.SEED_BASE + 3, args.cpu_modes)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

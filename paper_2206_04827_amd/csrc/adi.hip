@@ -15,8 +15,15 @@
 // first equation is step 1 of Algorithm 1 with X_{j+1/2} B eliminated through
 // step 2 (substitute (u C - A) Y = C W - E into Z = C^{-1}((v C - A) Y + E)).
 // Both sweeps work in place: the forward elimination overwrites the line with
-// its intermediate, the back substitution with the result, and the sliding
-// register windows hold the few neighbours still needed.
+// its intermediate, the back substitution with the result, and short register
+// windows hold the few neighbours still needed.
+//
+// Layouts of a parity block (me x ne, rows padded to mp, columns to np, both
+// multiples of G):
+//   E-layout  (E, residuals, heat history): column-major, element (i, k) at
+//             eoff + k * mp + i; rows me..mp-1 are zero.
+//   X-layout  (solutions):                  row-major, element (i, k) at
+//             xoff + i * ne + k.
 #include "kernels.hpp"
 
 namespace cyl {
@@ -25,189 +32,337 @@ namespace {
 constexpr int G = 8;          // rows per software-pipelined group
 constexpr int kRRec = 12;
 constexpr int kZRec = 8;
+constexpr int kPre = 24;      // coefficient doubles prefetched per thread
 
-// r-pass on column k (stride ld between rows) of a block with me rows.
-// RC: kRRec records per row; Ecol: E + k with row stride ne.
-__device__ __forceinline__ void adi_rpass(double* S, int ld, int me, int k,
-                                          const double* RC, const double* __restrict__ Ecol,
-                                          int ne, double vmu) {
-    // forward elimination: g_i = h_i - L_{i,i-1} g_{i-1} - L_{i,i-2} g_{i-2},
-    // h = (v C - A) w - (v - u) e.
+// ---------------------------------------------------------------------------
+// LDS-resident sweeps with a compile-time row stride LD (so every row offset
+// within a group is an instruction immediate).
+// ---------------------------------------------------------------------------
+
+// r-pass on column k.  S: state (rows padded to mp, followed by 4 zero guard
+// rows); RC: kRRec records per row; Ecol: this column of E (contiguous rows).
+// Each group of G rows first issues its record, window and E loads, then
+// evaluates the banded products (independent of the recurrence) for all rows,
+// then runs the dependent chain, one FMA deep per row.
+template <int LD>
+__device__ __forceinline__ void rpass_lds(double* __restrict__ S, int mp, int k,
+                                          const double* __restrict__ RC,
+                                          const double* __restrict__ Ecol, double vmu) {
+    const double2* E2 = reinterpret_cast<const double2*>(Ecol);
+    double* Sk = S + k;
     double wv[14];                 // rows i0-2 .. i0+11 of W
     wv[0] = 0.0; wv[1] = 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) wv[2 + q] = (q < me) ? S[q * ld + k] : 0.0;
-    double eb[G];
+    for (int q = 0; q < 4; ++q) wv[2 + q] = Sk[q * LD];
+    double2 eb[G / 2], en[G / 2];
 #pragma unroll
-    for (int q = 0; q < G; ++q) eb[q] = (q < me) ? Ecol[static_cast<int64_t>(q) * ne] : 0.0;
+    for (int q = 0; q < G / 2; ++q) { eb[q] = E2[q]; en[q] = E2[G / 2 + q]; }
     double g1 = 0.0, g2 = 0.0;
-    for (int i0 = 0; i0 < me; i0 += G) {
+    for (int i0 = 0; i0 < mp; i0 += G) {
+        double* Sg = Sk + i0 * LD;
+        const double* Rg = RC + i0 * kRRec;
+        double c[G][8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int r = i0 + 4 + q;
-            wv[6 + q] = (r < me) ? S[r * ld + k] : 0.0;
-        }
-        double en[G];
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) c[q][t] = Rg[q * kRRec + t];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) wv[6 + q] = Sg[(4 + q) * LD];
+        double2 enn[G / 2];
+#pragma unroll
+        for (int q = 0; q < G / 2; ++q) enn[q] = E2[(i0 + 2 * G) / 2 + q];
+        double e[G];
+#pragma unroll
+        for (int q = 0; q < G / 2; ++q) { e[2 * q] = eb[q].x; e[2 * q + 1] = eb[q].y; }
+        double h[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            h[q] = c[q][0] * wv[q] + c[q][1] * wv[q + 1] + c[q][2] * wv[q + 2] +
+                   c[q][3] * wv[q + 3] + c[q][4] * wv[q + 4] + c[q][5] * wv[q + 5] - vmu * e[q];
 #pragma unroll
         for (int q = 0; q < G; ++q) {
-            const int r = i0 + G + q;
-            en[q] = (r < me) ? Ecol[static_cast<int64_t>(r) * ne] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < G; ++q) {
-            const int i = i0 + q;
-            if (i < me) {
-                const double* rc = RC + i * kRRec;
-                double h = rc[0] * wv[q] + rc[1] * wv[q + 1] + rc[2] * wv[q + 2] +
-                           rc[3] * wv[q + 3] + rc[4] * wv[q + 4] + rc[5] * wv[q + 5] - vmu * eb[q];
-                h -= rc[6] * g2;
-                const double g = h - rc[7] * g1;
-                S[i * ld + k] = g;
-                g2 = g1;
-                g1 = g;
-            }
+            const double t = h[q] - c[q][6] * g2;
+            const double g = t - c[q][7] * g1;
+            Sg[q * LD] = g;
+            g2 = g1;
+            g1 = g;
         }
 #pragma unroll
         for (int q = 0; q < 6; ++q) wv[q] = wv[8 + q];
 #pragma unroll
-        for (int q = 0; q < G; ++q) eb[q] = en[q];
+        for (int q = 0; q < G / 2; ++q) { eb[q] = en[q]; en[q] = enn[q]; }
     }
     // back substitution: z_i = dinv_i g_i - sum_t (dinv_i U_{i,i+t}) z_{i+t}
-    const int ngr = (me + G - 1) / G;
     double gb[G];
-    {
-        const int i0 = (ngr - 1) * G;
 #pragma unroll
-        for (int q = 0; q < G; ++q) gb[q] = (i0 + q < me) ? S[(i0 + q) * ld + k] : 0.0;
-    }
+    for (int q = 0; q < G; ++q) gb[q] = Sk[(mp - G + q) * LD];
     double z1 = 0.0, z2 = 0.0, z3 = 0.0;
-    for (int gi = ngr - 1; gi >= 0; --gi) {
-        const int i0 = gi * G;
-        double gn[G];
+    for (int i0 = mp - G; i0 >= 0; i0 -= G) {
+        double* Sg = Sk + i0 * LD;
+        const double* Rg = RC + i0 * kRRec + 8;
+        double c[G][4];
 #pragma unroll
-        for (int q = 0; q < G; ++q) {
-            const int r = i0 - G + q;
-            gn[q] = (r >= 0) ? S[r * ld + k] : 0.0;
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) c[q][t] = Rg[q * kRRec + t];
+        double gn[G];
+        if (i0 > 0) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) gn[q] = Sg[(q - G) * LD];
         }
 #pragma unroll
         for (int q = G - 1; q >= 0; --q) {
-            const int i = i0 + q;
-            if (i < me) {
-                const double* rc = RC + i * kRRec;
-                const double t = rc[8] * gb[q] - rc[11] * z3 - rc[10] * z2;
-                const double z = t - rc[9] * z1;
-                S[i * ld + k] = z;
-                z3 = z2; z2 = z1; z1 = z;
-            }
+            const double t = c[q][0] * gb[q] - c[q][3] * z3 - c[q][2] * z2;
+            const double z = t - c[q][1] * z1;
+            Sg[q * LD] = z;
+            z3 = z2; z2 = z1; z1 = z;
         }
 #pragma unroll
         for (int q = 0; q < G; ++q) gb[q] = gn[q];
     }
 }
 
-// z-pass on one row (contiguous, ne entries).  ZC: kZRec records per column.
-__device__ __forceinline__ void adi_zpass(double* row, int ne, const double* ZC, bool last) {
-    // forward: g_k = z_k - L_k g_{k-1}
+// z-pass on one row (np columns, a multiple of G; columns beyond the block's
+// ne have zero records).  ZC: kZRec records per column.  The forward
+// prefetch may read past the row end (into the next row or the guard rows);
+// those values are never used.
+template <bool kLast>
+__device__ __forceinline__ void zpass_row(double* __restrict__ row, int np,
+                                          const double* __restrict__ ZC) {
     double zb[G];
 #pragma unroll
-    for (int q = 0; q < G; ++q) zb[q] = (q < ne) ? row[q] : 0.0;
+    for (int q = 0; q < G; ++q) zb[q] = row[q];
     double gp = 0.0;
-    for (int k0 = 0; k0 < ne; k0 += G) {
-        double zn[G];
+    for (int k0 = 0; k0 < np; k0 += G) {
+        double* rg = row + k0;
+        double l[G], zn[G];
 #pragma unroll
-        for (int q = 0; q < G; ++q) zn[q] = (k0 + G + q < ne) ? row[k0 + G + q] : 0.0;
+        for (int q = 0; q < G; ++q) l[q] = ZC[(k0 + q) * kZRec];
+#pragma unroll
+        for (int q = 0; q < G; ++q) zn[q] = rg[G + q];
 #pragma unroll
         for (int q = 0; q < G; ++q) {
-            const int k = k0 + q;
-            if (k < ne) {
-                const double g = zb[q] - ZC[k * kZRec] * gp;
-                row[k] = g;
-                gp = g;
-            }
+            const double g = zb[q] - l[q] * gp;
+            rg[q] = g;
+            gp = g;
         }
 #pragma unroll
         for (int q = 0; q < G; ++q) zb[q] = zn[q];
     }
     // back substitution x_k = dinv_k g_k - U1 x_{k+1} - U2 x_{k+2}, and unless
     // this is the last iteration, w_{k+1} = sum_t P_{k+1,t} x_{k+t}.
-    const int ngr = (ne + G - 1) / G;
     double gb[G];
-    {
-        const int k0 = (ngr - 1) * G;
 #pragma unroll
-        for (int q = 0; q < G; ++q) gb[q] = (k0 + q < ne) ? row[k0 + q] : 0.0;
-    }
+    for (int q = 0; q < G; ++q) gb[q] = row[np - G + q];
     double x1 = 0.0, x2 = 0.0, x3 = 0.0;
-    for (int gi = ngr - 1; gi >= 0; --gi) {
-        const int k0 = gi * G;
-        double gn[G];
+    double pn[4] = {0.0, 0.0, 0.0, 0.0};     // product record of column k0 + G
+    for (int k0 = np - G; k0 >= 0; k0 -= G) {
+        double* rg = row + k0;
+        const double* zg = ZC + k0 * kZRec;
+        double c[G][3], pr[G][4];
 #pragma unroll
         for (int q = 0; q < G; ++q) {
-            const int r = k0 - G + q;
-            gn[q] = (r >= 0) ? row[r] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) c[q][t] = zg[q * kZRec + 1 + t];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) pr[q][t] = zg[q * kZRec + 4 + t];
+        }
+        double gn[G];
+        if (k0 > 0) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) gn[q] = rg[q - G];
         }
 #pragma unroll
         for (int q = G - 1; q >= 0; --q) {
-            const int k = k0 + q;
-            if (k < ne) {
-                const double* zc = ZC + k * kZRec;
-                const double x = zc[1] * gb[q] - zc[3] * x2 - zc[2] * x1;
-                if (last) {
-                    row[k] = x;
-                } else if (k + 1 < ne) {
-                    const double* zn = zc + kZRec;
-                    row[k + 1] = zn[4] * x + zn[5] * x1 + zn[6] * x2 + zn[7] * x3;
-                }
-                x3 = x2; x2 = x1; x1 = x;
+            const double x = c[q][0] * gb[q] - c[q][2] * x2 - c[q][1] * x1;
+            if (kLast) {
+                rg[q] = x;
+            } else {
+                const double* p = (q == G - 1) ? pn : pr[q + 1];
+                if (q < G - 1 || k0 + G < np)
+                    rg[q + 1] = p[0] * x + p[1] * x1 + p[2] * x2 + p[3] * x3;
             }
+            x3 = x2; x2 = x1; x1 = x;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) pn[t] = pr[0][t];
+#pragma unroll
+        for (int q = 0; q < G; ++q) gb[q] = gn[q];
+    }
+    if (!kLast) row[0] = pn[1] * x1 + pn[2] * x2 + pn[3] * x3;
+}
+
+__device__ __forceinline__ void zpass(double* row, int np, const double* ZC, bool last) {
+    if (last) zpass_row<true>(row, np, ZC);
+    else zpass_row<false>(row, np, ZC);
+}
+
+// One workgroup per parity block, all J iterations, block state in LDS.
+// The records of shift j+1 are loaded into registers while shift j sweeps and
+// copied to LDS between iterations.
+template <int LD>
+__device__ __forceinline__ void adi_block_lds(double* sm, const BlockDesc& bd,
+                                              const double* __restrict__ E, double* X,
+                                              const double* __restrict__ rtab,
+                                              const double* __restrict__ ztab,
+                                              const double* __restrict__ vmu, int accumulate) {
+    const int me = bd.me, ne = bd.ne, mp = bd.mp, np = bd.np;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    double* S = sm;
+    double* RCs = sm + (mp + 4) * LD;
+    double* ZCs = RCs + mp * kRRec;
+    const int nr = mp * kRRec, nz = np * kZRec;
+    for (int idx = tid; idx < (mp + 4) * LD; idx += nt) S[idx] = 0.0;
+    double pre[kPre];
+    auto fetch = [&](int j) {
+        const double* rs = rtab + bd.rbase + j * bd.rstride;
+        const double* zs = ztab + bd.zbase + j * bd.zstride;
+#pragma unroll
+        for (int c = 0; c < kPre; ++c) {
+            const int idx = tid + c * nt;
+            pre[c] = idx < nr ? rs[idx] : (idx < nr + nz ? zs[idx - nr] : 0.0);
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int c = 0; c < kPre; ++c) {
+            const int idx = tid + c * nt;
+            if (idx < nr) RCs[idx] = pre[c];
+            else if (idx < nr + nz) ZCs[idx - nr] = pre[c];
+        }
+    };
+    fetch(0);
+    store();
+    __syncthreads();
+    const double* Ecol = E + bd.eoff + static_cast<int64_t>(tid) * mp;
+    for (int j = 0; j < bd.J; ++j) {
+        if (j + 1 < bd.J) fetch(j + 1);
+        const double vm = vmu[bd.soff + j];
+        if (tid < ne) rpass_lds<LD>(S, mp, tid, RCs, Ecol, vm);
+        __syncthreads();
+        if (tid < me) zpass(S + tid * LD, np, ZCs, j == bd.J - 1);
+        __syncthreads();
+        if (j + 1 < bd.J) {
+            store();
+            __syncthreads();
+        }
+    }
+    double* Xb = X + bd.xoff;
+    for (int idx = tid; idx < me * ne; idx += nt) {
+        const int i = idx / ne, k = idx - i * ne;
+        const double v = S[i * LD + k];
+        Xb[idx] = accumulate ? Xb[idx] + v : v;
+    }
+}
+
+template <int NP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_adi_lds(const BlockDesc* __restrict__ blocks, const double* __restrict__ E, double* X,
+               const double* __restrict__ rtab, const double* __restrict__ ztab,
+               const double* __restrict__ vmu, int accumulate) {
+    extern __shared__ double sm[];
+    const BlockDesc bd = blocks[blockIdx.x];
+    adi_block_lds<NP + 1>(sm, bd, E, X, rtab, ztab, vmu, accumulate);
+}
+
+// ---------------------------------------------------------------------------
+// HBM-resident variant (blocks too large for LDS): runtime strides; the
+// state of block b lives at state + b * state_stride (rows padded to mp,
+// columns to np, row stride np + 1, 4 guard rows), records are read from the
+// tables directly.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void rpass_gen(double* __restrict__ S, int ld, int mp, int k,
+                                          const double* __restrict__ RC,
+                                          const double* __restrict__ Ecol, double vmu) {
+    auto erow = [&](int r) { return Ecol[min(r, mp - 1)]; };
+    double* Sk = S + k;
+    double wv[14];
+    wv[0] = 0.0; wv[1] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wv[2 + q] = Sk[q * ld];
+    double eb[G], en[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) { eb[q] = erow(q); en[q] = erow(G + q); }
+    double g1 = 0.0, g2 = 0.0;
+    for (int i0 = 0; i0 < mp; i0 += G) {
+        double c[G][8];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) c[q][t] = RC[(i0 + q) * kRRec + t];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) wv[6 + q] = Sk[(i0 + 4 + q) * ld];
+        double enn[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) enn[q] = erow(i0 + 2 * G + q);
+        double h[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            h[q] = c[q][0] * wv[q] + c[q][1] * wv[q + 1] + c[q][2] * wv[q + 2] +
+                   c[q][3] * wv[q + 3] + c[q][4] * wv[q + 4] + c[q][5] * wv[q + 5] - vmu * eb[q];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double t = h[q] - c[q][6] * g2;
+            const double g = t - c[q][7] * g1;
+            Sk[(i0 + q) * ld] = g;
+            g2 = g1;
+            g1 = g;
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) wv[q] = wv[8 + q];
+#pragma unroll
+        for (int q = 0; q < G; ++q) { eb[q] = en[q]; en[q] = enn[q]; }
+    }
+    double gb[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) gb[q] = Sk[(mp - G + q) * ld];
+    double z1 = 0.0, z2 = 0.0, z3 = 0.0;
+    for (int i0 = mp - G; i0 >= 0; i0 -= G) {
+        double c[G][4];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) c[q][t] = RC[(i0 + q) * kRRec + 8 + t];
+        double gn[G];
+        if (i0 > 0) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) gn[q] = Sk[(i0 - G + q) * ld];
+        }
+#pragma unroll
+        for (int q = G - 1; q >= 0; --q) {
+            const double t = c[q][0] * gb[q] - c[q][3] * z3 - c[q][2] * z2;
+            const double z = t - c[q][1] * z1;
+            Sk[(i0 + q) * ld] = z;
+            z3 = z2; z2 = z1; z1 = z;
         }
 #pragma unroll
         for (int q = 0; q < G; ++q) gb[q] = gn[q];
     }
-    if (!last) row[0] = ZC[5] * x1 + ZC[6] * x2 + ZC[7] * x3;
 }
 
-// One workgroup per parity block, all J iterations.  kLDS: block state and
-// the current shift's coefficient records live in LDS; otherwise the state
-// lives in `state` (same offsets as E) and records are read from the tables.
-template <bool kLDS>
-__device__ __forceinline__ void adi_block(double* sm, const BlockDesc* __restrict__ blocks,
-                                          const double* __restrict__ E, double* X,
-                                          double* state, const double* __restrict__ rtab,
-                                          const double* __restrict__ ztab,
-                                          const double* __restrict__ vmu, int accumulate) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_adi_global(const BlockDesc* __restrict__ blocks, const double* __restrict__ E, double* X,
+                  double* state, int64_t state_stride, const double* __restrict__ rtab,
+                  const double* __restrict__ ztab, const double* __restrict__ vmu,
+                  int accumulate) {
     const BlockDesc bd = blocks[blockIdx.x];
-    const int me = bd.me, ne = bd.ne;
+    const int me = bd.me, ne = bd.ne, mp = bd.mp, np = bd.np;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int ld = kLDS ? (ne | 1) : ne;
-    double* S = kLDS ? sm : state + bd.eoff;
-    double* RCs = sm + me * ld;
-    double* ZCs = RCs + me * kRRec;
-    for (int idx = tid; idx < me * ld; idx += nt) S[idx] = 0.0;
-    const double* Eb = E + bd.eoff;
+    const int ld = np + 1;
+    double* S = state + static_cast<int64_t>(blockIdx.x) * state_stride;
+    for (int idx = tid; idx < (mp + 4) * ld; idx += nt) S[idx] = 0.0;
+    const double* Ecol = E + bd.eoff + static_cast<int64_t>(tid) * mp;
     for (int j = 0; j < bd.J; ++j) {
-        const double* rsrc = rtab + bd.rbase + j * bd.rstride;
-        const double* zsrc = ztab + bd.zbase + j * bd.zstride;
-        const double* RC;
-        const double* ZC;
-        __syncthreads();
-        if (kLDS) {
-            for (int idx = tid; idx < me * kRRec; idx += nt) RCs[idx] = rsrc[idx];
-            for (int idx = tid; idx < ne * kZRec; idx += nt) ZCs[idx] = zsrc[idx];
-            __syncthreads();
-            RC = RCs;
-            ZC = ZCs;
-        } else {
-            RC = rsrc;
-            ZC = zsrc;
-        }
+        const double* RC = rtab + bd.rbase + j * bd.rstride;
+        const double* ZC = ztab + bd.zbase + j * bd.zstride;
         const double vm = vmu[bd.soff + j];
-        if (tid < ne) adi_rpass(S, ld, me, tid, RC, Eb + tid, ne, vm);
         __syncthreads();
-        if (tid < me) adi_zpass(S + tid * ld, ne, ZC, j == bd.J - 1);
+        if (tid < ne) rpass_gen(S, ld, mp, tid, RC, Ecol, vm);
+        __syncthreads();
+        if (tid < me) zpass(S + tid * ld, np, ZC, j == bd.J - 1);
     }
     __syncthreads();
-    double* Xb = X + bd.eoff;
+    double* Xb = X + bd.xoff;
     for (int idx = tid; idx < me * ne; idx += nt) {
         const int i = idx / ne, k = idx - i * ne;
         const double v = S[i * ld + k];
@@ -215,29 +370,10 @@ __device__ __forceinline__ void adi_block(double* sm, const BlockDesc* __restric
     }
 }
 
-__global__ __launch_bounds__(256) void k_adi_lds(const BlockDesc* __restrict__ blocks,
-                                                 const double* __restrict__ E, double* X,
-                                                 double* state, const double* __restrict__ rtab,
-                                                 const double* __restrict__ ztab,
-                                                 const double* __restrict__ vmu, int accumulate) {
-    extern __shared__ double sm[];
-    adi_block<true>(sm, blocks, E, X, state, rtab, ztab, vmu, accumulate);
-}
-
-__global__ __launch_bounds__(1024) void k_adi_global(const BlockDesc* __restrict__ blocks,
-                                                     const double* __restrict__ E, double* X,
-                                                     double* state,
-                                                     const double* __restrict__ rtab,
-                                                     const double* __restrict__ ztab,
-                                                     const double* __restrict__ vmu,
-                                                     int accumulate) {
-    adi_block<false>(nullptr, blocks, E, X, state, rtab, ztab, vmu, accumulate);
-}
-
 // ---------------------------------------------------------------------------
 // tau right-hand side (eq. HelmholtzMatEqn, right side, with r^2 weighting):
 //   E = sF [R2 (F + cL L) C02^T]_tau + sL [A_w L C02^T + R2 L D2^T]_tau
-// written into the parity blocks of each real mode plane (L may be NULL).
+// written into the parity blocks (E-layout) of each real mode plane.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_rhs(const double2* __restrict__ F,
                                              const double2* __restrict__ L, double sF, double cL,
@@ -302,7 +438,7 @@ __global__ __launch_bounds__(256) void k_rhs(const double2* __restrict__ F,
         acc += sL * lacc;
     }
     const BlockDesc bd = blocks[4 * plane + 2 * (i & 1) + (k & 1)];
-    E[bd.eoff + static_cast<int64_t>(i >> 1) * bd.ne + (k >> 1)] = acc;
+    E[bd.eoff + static_cast<int64_t>(k >> 1) * bd.mp + (i >> 1)] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -312,7 +448,7 @@ __device__ __forceinline__ double xt_at(const double* X, const BlockDesc* blocks
                                         int i, int k, int mi, int ni) {
     if (plane < 0 || i < 0 || k < 0 || i >= mi || k >= ni) return 0.0;
     const BlockDesc& bd = blocks[4 * plane + 2 * (i & 1) + (k & 1)];
-    return X[bd.eoff + static_cast<int64_t>(i >> 1) * bd.ne + (k >> 1)];
+    return X[bd.xoff + static_cast<int64_t>(i >> 1) * bd.ne + (k >> 1)];
 }
 
 __global__ __launch_bounds__(256) void k_recombine(const double* __restrict__ X,
@@ -344,41 +480,56 @@ __global__ __launch_bounds__(256) void k_recombine(const double* __restrict__ X,
 }
 
 // ---------------------------------------------------------------------------
-// out = sE E - sAB (A X B) - sCD (C X D), blockwise.
+// out = sE E - sAB (A X B) - sCD (C X D), blockwise; X in X-layout, E and out
+// in E-layout.  One workgroup per 32 x 32 output tile; the X tile with its
+// halo (rows -2..+3, columns -1..+2) is staged in LDS.
 // ---------------------------------------------------------------------------
+constexpr int kTile = 32;
+constexpr int kTR = kTile + 5, kTC = kTile + 3;
+
 __global__ __launch_bounds__(256) void k_apply(const BlockDesc* __restrict__ blocks,
                                                const double* __restrict__ E, double sE,
                                                const double* __restrict__ X, double sAB,
                                                double sCD, double* __restrict__ out,
                                                const double* __restrict__ atab, int64_t a_wstride,
                                                int me0, const double* __restrict__ ztabA, int ne0) {
-    const BlockDesc bd = blocks[blockIdx.y];
+    __shared__ double xs[kTR][kTC + 1];
+    const BlockDesc bd = blocks[blockIdx.z];
     const int me = bd.me, ne = bd.ne;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= me * ne) return;
-    const int i = e / ne, k = e - i * ne;
-    const double* Xb = X + bd.eoff;
-    const double* ar = atab + bd.w * a_wstride + (bd.pr ? me0 * 12 : 0) + i * 12;
-    const double* zc = ztabA + (bd.pz ? ne0 * 8 : 0) + k * 8;
-    double sab = 0.0, scd = 0.0;
-#pragma unroll
-    for (int da = -2; da <= 3; ++da) {
-        const int a = i + da;
-        if (a < 0 || a >= me) continue;
-        double xb = 0.0, xd = 0.0;
-#pragma unroll
-        for (int dl = -1; dl <= 2; ++dl) {
-            const int l = k + dl;
-            if (l < 0 || l >= ne) continue;
-            const double x = Xb[a * ne + l];
-            xb += x * zc[dl + 1];
-            xd += x * zc[4 + dl + 1];
-        }
-        sab += ar[da + 2] * xb;
-        scd += ar[6 + da + 2] * xd;
+    const int i0 = blockIdx.x * kTile, k0 = blockIdx.y * kTile;
+    if (i0 >= me || k0 >= ne) return;
+    const double* Xb = X + bd.xoff;
+    for (int idx = threadIdx.x; idx < kTR * kTC; idx += blockDim.x) {
+        const int r = idx / kTC, c = idx - r * kTC;
+        const int a = i0 - 2 + r, l = k0 - 1 + c;
+        xs[r][c] = (a >= 0 && a < me && l >= 0 && l < ne) ? Xb[static_cast<int64_t>(a) * ne + l] : 0.0;
     }
-    const double ev = (sE != 0.0) ? sE * E[bd.eoff + e] : 0.0;
-    out[bd.eoff + e] = ev - sAB * sab - sCD * scd;
+    __syncthreads();
+    const double* arow = atab + bd.w * a_wstride + (bd.pr ? me0 * 12 : 0);
+    const double* zcol = ztabA + (bd.pz ? ne0 * 8 : 0);
+    for (int idx = threadIdx.x; idx < kTile * kTile; idx += blockDim.x) {
+        const int di = idx % kTile, dk = idx / kTile;
+        const int i = i0 + di, k = k0 + dk;
+        if (i >= me || k >= ne) continue;
+        const double* ar = arow + i * 12;
+        const double* zc = zcol + k * 8;
+        double sab = 0.0, scd = 0.0;
+#pragma unroll
+        for (int da = 0; da < 6; ++da) {
+            double xb = 0.0, xd = 0.0;
+#pragma unroll
+            for (int dl = 0; dl < 4; ++dl) {
+                const double x = xs[di + da][dk + dl];
+                xb += x * zc[dl];
+                xd += x * zc[4 + dl];
+            }
+            sab += ar[da] * xb;
+            scd += ar[6 + da] * xd;
+        }
+        const int64_t o = bd.eoff + static_cast<int64_t>(k) * bd.mp + i;
+        const double ev = (sE != 0.0) ? sE * E[o] : 0.0;
+        out[o] = ev - sAB * sab - sCD * scd;
+    }
 }
 
 struct PList { const double* p[4]; double beta[4]; };
@@ -393,18 +544,19 @@ __global__ __launch_bounds__(256) void k_heat_rhs(double* __restrict__ E, PList 
 }
 
 __global__ __launch_bounds__(256) void k_norms(const double* __restrict__ R,
-                                               const double* __restrict__ E,
-                                               const double* __restrict__ X, int64_t total,
+                                               const double* __restrict__ E, int64_t etotal,
+                                               const double* __restrict__ X, int64_t xtotal,
                                                double* acc) {
     __shared__ double red[3][256];
     double r2 = 0.0, e2 = 0.0, bad = 0.0;
-    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const double r = R[e], ev = E[e], x = X[e];
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < etotal; e += stride) {
+        const double r = R[e], ev = E[e];
         r2 += r * r;
         e2 += ev * ev;
-        if (!isfinite(x)) bad += 1.0;
     }
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < xtotal; e += stride)
+        if (!isfinite(X[e])) bad += 1.0;
     red[0][threadIdx.x] = r2; red[1][threadIdx.x] = e2; red[2][threadIdx.x] = bad;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -415,24 +567,50 @@ __global__ __launch_bounds__(256) void k_norms(const double* __restrict__ R,
     if (threadIdx.x < 3) atomicAdd(&acc[threadIdx.x], red[threadIdx.x][0]);
 }
 
-}  // namespace
-
-hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, const double* E,
-                      double* X, double* state, const double* rtab, const double* ztab,
-                      const double* vmu, bool accumulate, bool use_lds, size_t lds_bytes,
-                      hipStream_t s) {
-    if (use_lds)
-        hipLaunchKernelGGL(k_adi_lds, dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
-                           state, rtab, ztab, vmu, accumulate ? 1 : 0);
-    else
-        hipLaunchKernelGGL(k_adi_global, dim3(nblocks), dim3(threads), 0, s, blocks, E, X, state,
-                           rtab, ztab, vmu, accumulate ? 1 : 0);
+template <int NP>
+hipError_t launch_lds(const BlockDesc* blocks, int nblocks, int threads, const double* E,
+                      double* X, const double* rtab, const double* ztab, const double* vmu,
+                      bool accumulate, size_t lds_bytes, hipStream_t s) {
+    hipLaunchKernelGGL(k_adi_lds<NP>, dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
+                       rtab, ztab, vmu, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t adi_set_lds_limit(size_t bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_lds),
+template <int NP>
+hipError_t set_limit(size_t bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_lds<NP>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+}
+
+}  // namespace
+
+#define CYL_NP_CASES(X) X(8) X(16) X(24) X(32) X(40) X(48) X(56) X(64) X(72) X(80) X(88) X(96) \
+    X(104) X(112) X(120) X(128)
+
+hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, int np0, const double* E,
+                      double* X, double* state, int64_t state_stride, const double* rtab,
+                      const double* ztab, const double* vmu, bool accumulate, bool use_lds,
+                      size_t lds_bytes, hipStream_t s) {
+    if (use_lds) {
+        switch (np0) {
+#define CYL_CASE(v) case v: return launch_lds<v>(blocks, nblocks, threads, E, X, rtab, ztab, vmu, accumulate, lds_bytes, s);
+            CYL_NP_CASES(CYL_CASE)
+#undef CYL_CASE
+            default: return hipErrorInvalidValue;
+        }
+    }
+    hipLaunchKernelGGL(k_adi_global, dim3(nblocks), dim3(threads), 0, s, blocks, E, X, state,
+                       state_stride, rtab, ztab, vmu, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t adi_set_lds_limit(int np0, size_t bytes) {
+    switch (np0) {
+#define CYL_CASE(v) case v: return set_limit<v>(bytes);
+        CYL_NP_CASES(CYL_CASE)
+#undef CYL_CASE
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_rhs3(const double2* F, const double2* L, double sF, double cL, double sL,
@@ -454,11 +632,12 @@ hipError_t launch_recombine(const double* X, const double2* L, double2* planes,
     return hipGetLastError();
 }
 
-hipError_t launch_apply2(const BlockDesc* blocks, int nblocks, int max_elems, const double* E,
+hipError_t launch_apply2(const BlockDesc* blocks, int nblocks, int me0, int ne0, const double* E,
                          double sE, const double* X, double sAB, double sCD, double* out,
-                         const double* atab, int64_t a_wstride, int me0, const double* ztabA,
-                         int ne0, hipStream_t s) {
-    const dim3 grid(static_cast<unsigned>((max_elems + 255) / 256), nblocks);
+                         const double* atab, int64_t a_wstride, const double* ztabA,
+                         hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>((me0 + kTile - 1) / kTile),
+                    static_cast<unsigned>((ne0 + kTile - 1) / kTile), nblocks);
     hipLaunchKernelGGL(k_apply, grid, dim3(256), 0, s, blocks, E, sE, X, sAB, sCD, out, atab,
                        a_wstride, me0, ztabA, ne0);
     return hipGetLastError();
@@ -473,13 +652,13 @@ hipError_t launch_heat_rhs(double* E, const double* const* P, const double* beta
     return hipGetLastError();
 }
 
-hipError_t launch_norms(const double* R, const double* E, const double* X, int64_t total,
-                        double* acc, hipStream_t s) {
-    int64_t blocks = (total + 255) / 256;
+hipError_t launch_norms(const double* R, const double* E, int64_t etotal, const double* X,
+                        int64_t xtotal, double* acc, hipStream_t s) {
+    int64_t blocks = (etotal + 255) / 256;
     if (blocks > 2048) blocks = 2048;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_norms, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, R, E, X,
-                       total, acc);
+    hipLaunchKernelGGL(k_norms, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, R, E, etotal,
+                       X, xtotal, acc);
     return hipGetLastError();
 }
 

@@ -127,6 +127,7 @@ struct cyl_plan_s {
     DevMem plane_of, ztabA, atab_proj;
     DevMem planesA, planesB, E, X, R, state, acc;
     bool use_lds = false;
+    int64_t state_stride = 0;
     int adi_threads = 64;
     size_t lds_bytes = 0;
     std::map<std::pair<double, int>, std::unique_ptr<Setup>> setups;
@@ -193,21 +194,26 @@ std::unique_ptr<Setup> make_setup(cyl_plan_t pl, double ka, double eps) {
     s->h = build_adi_setup(pl->geo, pl->rops, pl->zops, ka, eps_pass);
     const Geometry& g = pl->geo;
     const int me0 = g.me[0], me1 = g.me[1], ne0 = g.ne[0], ne1 = g.ne[1];
-    const int64_t blk_off[4] = {0, static_cast<int64_t>(me0) * ne0,
-                                static_cast<int64_t>(me0) * ne0 + static_cast<int64_t>(me0) * ne1,
-                                static_cast<int64_t>(me0) * (ne0 + ne1) + static_cast<int64_t>(me1) * ne0};
+    // block offsets inside a plane: (pr, pz) = (0,0), (0,1), (1,0), (1,1)
+    const int64_t eblk[4] = {0, static_cast<int64_t>(g.mp[0]) * ne0,
+                             static_cast<int64_t>(g.mp[0]) * (ne0 + ne1),
+                             static_cast<int64_t>(g.mp[0]) * (ne0 + ne1) + static_cast<int64_t>(g.mp[1]) * ne0};
+    const int64_t xblk[4] = {0, static_cast<int64_t>(me0) * ne0, static_cast<int64_t>(me0) * (ne0 + ne1),
+                             static_cast<int64_t>(me0) * (ne0 + ne1) + static_cast<int64_t>(me1) * ne0};
     for (int pl_i = 0; pl_i < g.nplanes; ++pl_i) {
         const int w = g.plane_w[pl_i];
         for (int pr = 0; pr < 2; ++pr)
             for (int pz = 0; pz < 2; ++pz) {
                 BlockDesc b{};
                 b.w = w; b.J = s->h.J[w]; b.me = g.me[pr]; b.ne = g.ne[pz];
+                b.mp = g.mp[pr]; b.np = g.np[pz];
                 b.pr = pr; b.pz = pz; b.part = g.plane_part[pl_i]; b.plane = pl_i;
-                b.eoff = pl_i * g.plane_elems + blk_off[2 * pr + pz];
-                b.rstride = static_cast<int64_t>(me0 + me1) * kRRec;
-                b.zstride = static_cast<int64_t>(ne0 + ne1) * kZRec;
-                b.rbase = s->h.roff[w] + (pr ? static_cast<int64_t>(me0) * kRRec : 0);
-                b.zbase = s->h.zoff[w] + (pz ? static_cast<int64_t>(ne0) * kZRec : 0);
+                b.eoff = pl_i * g.eplane_elems + eblk[2 * pr + pz];
+                b.xoff = pl_i * g.plane_elems + xblk[2 * pr + pz];
+                b.rstride = static_cast<int64_t>(g.mp[0] + g.mp[1]) * kRRec;
+                b.zstride = static_cast<int64_t>(g.np[0] + g.np[1]) * kZRec;
+                b.rbase = s->h.roff[w] + (pr ? static_cast<int64_t>(g.mp[0]) * kRRec : 0);
+                b.zbase = s->h.zoff[w] + (pz ? static_cast<int64_t>(g.np[0]) * kZRec : 0);
                 b.soff = s->h.soff[w];
                 s->hblocks.push_back(b);
             }
@@ -247,6 +253,13 @@ Setup* poisson_setup(cyl_plan_t pl, double eps) {
     Setup* raw = s.get();
     pl->setups[key] = std::move(s);
     return raw;
+}
+
+// E-layout buffer: zero padding rows, plus read-ahead slack after the end.
+void alloc_elayout(DevMem& m, const Geometry& g) {
+    const size_t bytes = (static_cast<size_t>(g.etotal_elems) + 64) * sizeof(double);
+    m.alloc(bytes);
+    hip_check(hipMemset(m.p, 0, bytes), "hipMemset");
 }
 
 // ---------------------------------------------------------------------------
@@ -291,20 +304,20 @@ void transform_inv(cyl_plan_t pl, const double2* coeffs, double* values) {
 void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X) {
     const Geometry& g = pl->geo;
     const int nblk = static_cast<int>(s->hblocks.size());
-    const int max_elems = g.me[0] * g.ne[0];
     for (int pass = 0; pass < s->passes; ++pass) {
         const double* rhs = E;
         if (pass > 0) {
             Scope sc(pl, PH_RES);
-            hip_check(launch_apply2(s->blocks.as<BlockDesc>(), nblk, max_elems, E, 1.0, X, 1.0, 1.0,
+            hip_check(launch_apply2(s->blocks.as<BlockDesc>(), nblk, g.me[0], g.ne[0], E, 1.0, X, 1.0, 1.0,
                                     pl->R.as<double>(), s->atab.as<double>(),
-                                    static_cast<int64_t>(g.me[0] + g.me[1]) * 12, g.me[0],
-                                    pl->ztabA.as<double>(), g.ne[0], pl->stream), "residual");
+                                    static_cast<int64_t>(g.me[0] + g.me[1]) * 12,
+                                    pl->ztabA.as<double>(), pl->stream), "residual");
             rhs = pl->R.as<double>();
         }
         Scope sc(pl, PH_ADI);
-        hip_check(launch_adi(s->blocks.as<BlockDesc>(), nblk, pl->adi_threads, rhs, X,
-                             pl->state.as<double>(), s->rtab.as<double>(), s->ztab.as<double>(),
+        hip_check(launch_adi(s->blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
+                             pl->state.as<double>(), pl->state_stride, s->rtab.as<double>(),
+                             s->ztab.as<double>(),
                              s->vmu.as<double>(), pass > 0, pl->use_lds, pl->lds_bytes, pl->stream),
                   "adi");
     }
@@ -316,13 +329,14 @@ void check_residual(cyl_plan_t pl, Setup* s, const double* E, const double* X, d
     const int nblk = static_cast<int>(s->hblocks.size());
     {
         Scope sc(pl, PH_RES);
-        hip_check(launch_apply2(s->blocks.as<BlockDesc>(), nblk, g.me[0] * g.ne[0], E, 1.0, X, 1.0, 1.0,
+        hip_check(launch_apply2(s->blocks.as<BlockDesc>(), nblk, g.me[0], g.ne[0], E, 1.0, X, 1.0, 1.0,
                                 pl->R.as<double>(), s->atab.as<double>(),
-                                static_cast<int64_t>(g.me[0] + g.me[1]) * 12, g.me[0],
-                                pl->ztabA.as<double>(), g.ne[0], pl->stream), "residual");
+                                static_cast<int64_t>(g.me[0] + g.me[1]) * 12,
+                                pl->ztabA.as<double>(), pl->stream), "residual");
     }
     hip_check(hipMemsetAsync(pl->acc.p, 0, 3 * sizeof(double), pl->stream), "memset");
-    hip_check(launch_norms(pl->R.as<double>(), E, X, g.total_elems, pl->acc.as<double>(), pl->stream), "norms");
+    hip_check(launch_norms(pl->R.as<double>(), E, g.etotal_elems, X, g.total_elems, pl->acc.as<double>(),
+                           pl->stream), "norms");
     double h[3];
     hip_check(hipMemcpyAsync(h, pl->acc.p, sizeof(h), hipMemcpyDeviceToHost, pl->stream), "copy norms");
     hip_check(hipStreamSynchronize(pl->stream), "sync");
@@ -420,14 +434,15 @@ void build_plan(cyl_plan_t pl) {
     const size_t blk_bytes = static_cast<size_t>(g.total_elems) * sizeof(double);
     pl->planesA.alloc(planes_bytes);
     pl->planesB.alloc(planes_bytes);
-    pl->E.alloc(blk_bytes);
+    alloc_elayout(pl->E, g);
     pl->X.alloc(blk_bytes);
-    pl->R.alloc(blk_bytes);
+    alloc_elayout(pl->R, g);
     pl->acc.alloc(4 * sizeof(double));
     // ADI variant: LDS-resident when the largest block and its records fit
     pl->adi_threads = ((std::max(g.me[0], g.ne[0]) + 63) / 64) * 64;
-    pl->lds_bytes = (static_cast<size_t>(g.me[0]) * (g.ne[0] | 1) + static_cast<size_t>(kRRec) * g.me[0] +
-                     static_cast<size_t>(kZRec) * g.ne[0]) * sizeof(double);
+    pl->state_stride = static_cast<int64_t>(g.mp[0] + 4) * (g.np[0] + 1);
+    pl->lds_bytes = (static_cast<size_t>(pl->state_stride) + static_cast<size_t>(kRRec) * g.mp[0] +
+                     static_cast<size_t>(kZRec) * g.np[0]) * sizeof(double);
     int dev = 0, max_lds = 0;
     hip_check(hipGetDevice(&dev), "hipGetDevice");
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 65536;
@@ -435,16 +450,18 @@ void build_plan(cyl_plan_t pl) {
     if (hipDeviceGetAttribute(&max_lds_sm, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess)
         max_lds = std::max(max_lds, max_lds_sm);
     const int mode = env_int("CYLSPEC_ADI_GLOBAL", 0);
-    pl->use_lds = mode == 0 && pl->adi_threads <= 256 && pl->lds_bytes <= static_cast<size_t>(max_lds);
+    pl->use_lds = mode == 0 && pl->adi_threads <= 256 && g.np[0] <= 128 &&
+                  pl->lds_bytes <= static_cast<size_t>(max_lds) &&
+                  static_cast<int>(kRRec * g.mp[0] + kZRec * g.np[0]) <= 24 * pl->adi_threads;
     if (pl->use_lds && pl->lds_bytes > 65536) {
-        if (adi_set_lds_limit(pl->lds_bytes) != hipSuccess) {
+        if (adi_set_lds_limit(g.np[0], pl->lds_bytes) != hipSuccess) {
             (void)hipGetLastError();
             pl->use_lds = false;
         }
     }
     if (!pl->use_lds) {
-        pl->adi_threads = std::min(1024, pl->adi_threads);
-        pl->state.alloc(blk_bytes);
+        pl->adi_threads = std::min(512, pl->adi_threads);
+        pl->state.alloc(static_cast<size_t>(4 * g.nplanes) * pl->state_stride * sizeof(double));
     }
     if (env_int("CYLSPEC_LOG", 0) > 0)
         std::fprintf(stderr, "[cylspec] plan %dx%dx%d: blocks me=(%d,%d) ne=(%d,%d), ADI %s, %d threads, "
@@ -579,8 +596,8 @@ int cyl_heat_create(cyl_heat_t* h, cyl_plan_t plan, double alpha, double dt, int
         H->setup = make_setup(pl, ka, adi_tol);
         const size_t blk_bytes = static_cast<size_t>(geo.total_elems) * sizeof(double);
         const size_t planes_bytes = static_cast<size_t>(geo.nw) * geo.n * geo.m * sizeof(double2);
-        for (int i = 0; i < bdf_order; ++i) H->P[i].alloc(blk_bytes);
-        H->Econst.alloc(blk_bytes);
+        for (int i = 0; i < bdf_order; ++i) alloc_elayout(H->P[i], geo);
+        alloc_elayout(H->Econst, geo);
         H->Xt.alloc(blk_bytes);
         H->T0.alloc(planes_bytes);
         const BlockDesc* blocks = H->setup->blocks.as<BlockDesc>();
@@ -639,17 +656,17 @@ int cyl_heat_step(cyl_heat_t h, int n_steps) {
             {
                 Scope sc(pl, PH_HRHS);
                 hip_check(launch_heat_rhs(pl->E.as<double>(), P, h->beta, h->order, h->Econst.as<double>(),
-                                          g.total_elems, pl->stream), "heat rhs");
+                                          g.etotal_elems, pl->stream), "heat rhs");
             }
             adi_solve(pl, s, pl->E.as<double>(), h->Xt.as<double>());
             // the oldest slot becomes the newest: P_new = C~ Xt B~
             const int slot = (h->head + h->order - 1) % h->order;
             {
                 Scope sc(pl, PH_PROJ);
-                hip_check(launch_apply2(s->blocks.as<BlockDesc>(), nblk, g.me[0] * g.ne[0], nullptr, 0.0,
+                hip_check(launch_apply2(s->blocks.as<BlockDesc>(), nblk, g.me[0], g.ne[0], nullptr, 0.0,
                                         h->Xt.as<double>(), -1.0, 0.0, h->P[slot].as<double>(),
-                                        pl->atab_proj.as<double>(), 0, g.me[0], pl->ztabA.as<double>(),
-                                        g.ne[0], pl->stream), "project");
+                                        pl->atab_proj.as<double>(), 0, pl->ztabA.as<double>(),
+                                        pl->stream), "project");
             }
             h->head = slot;
             ++h->steps;

@@ -23,10 +23,14 @@ struct LineSet {
 };
 
 // One ADI work item: a parity block (w, part, pr, pz) of a real mode plane.
+// E-layout (right-hand sides, residuals, heat history): column-major with the
+// rows padded to mp, element (i, k) at eoff + k * mp + i, padding rows zero.
+// X-layout (solutions): row-major, element (i, k) at xoff + i * ne + k.
 struct BlockDesc {
     int w, J, me, ne;
+    int mp, np;              // me, ne rounded up to multiples of 8
     int pr, pz, part, plane;
-    int64_t eoff;            // offset of the block in E / X (doubles)
+    int64_t eoff, xoff;
     int64_t rbase, zbase;    // offset of (j = 0) records in rtab / ztab
     int64_t rstride, zstride;// record stride between successive shifts
     int64_t soff;            // offset of v_j - u_j values
@@ -60,30 +64,37 @@ hipError_t launch_recombine(const double* X, const double2* L, double2* planes,
                             int m, int n, int p, hipStream_t s);
 
 // ---- ADI (Algorithm 1) ----
-hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, const double* E,
-                      double* X, double* state, const double* rtab, const double* ztab,
-                      const double* vmu, bool accumulate, bool use_lds, size_t lds_bytes,
-                      hipStream_t s);
+// Coefficient tables hold, per parity block, rows padded to a multiple of 8
+// (zero records beyond the block).  state: HBM-resident variant only,
+// state_stride doubles per block.
+// np0: padded width of the widest block (selects the LDS kernel instance;
+// multiples of 8 up to 128).  E-layout buffers need 64 doubles of slack
+// after their end (read-ahead of the sweeps; values unused).
+hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, int np0, const double* E,
+                      double* X, double* state, int64_t state_stride, const double* rtab,
+                      const double* ztab, const double* vmu, bool accumulate, bool use_lds,
+                      size_t lds_bytes, hipStream_t s);
 
-// Raise the dynamic-LDS limit of the LDS-resident ADI kernel.
-hipError_t adi_set_lds_limit(size_t bytes);
+// Raise the dynamic-LDS limit of the LDS-resident ADI kernel for width np0.
+hipError_t adi_set_lds_limit(int np0, size_t bytes);
 
 // out = sE * E - sAB * (A X B) - sCD * (C X D) blockwise.  atab: per (w, r
 // parity) rows of 12 (A row i at i-2..i+3, then C row i at i-2..i+3), w stride
 // a_wstride (0: the same rows for every w); ztabA: per z parity columns of 8
 // (B column k at rows k-1..k+2, then D column k at rows k-1..k+2).
-hipError_t launch_apply2(const BlockDesc* blocks, int nblocks, int max_elems, const double* E,
+hipError_t launch_apply2(const BlockDesc* blocks, int nblocks, int me0, int ne0, const double* E,
                          double sE, const double* X, double sAB, double sCD, double* out,
-                         const double* atab, int64_t a_wstride, int me0, const double* ztabA,
-                         int ne0, hipStream_t s);
+                         const double* atab, int64_t a_wstride, const double* ztabA,
+                         hipStream_t s);
 
 // ---- heat ----
 hipError_t launch_heat_rhs(double* E, const double* const* P, const double* beta, int nb,
                            const double* Econst, int64_t total, hipStream_t s);
 
 // ---- reductions ----
-// acc[0] += sum R^2, acc[1] += sum E^2, acc[2] += count of non-finite X
-hipError_t launch_norms(const double* R, const double* E, const double* X, int64_t total,
-                        double* acc, hipStream_t s);
+// acc[0] += sum R^2, acc[1] += sum E^2 (E-layout, etotal entries),
+// acc[2] += count of non-finite X (X-layout, xtotal entries)
+hipError_t launch_norms(const double* R, const double* E, int64_t etotal, const double* X,
+                        int64_t xtotal, double* acc, hipStream_t s);
 
 }  // namespace cyl

@@ -389,6 +389,10 @@ Geometry make_geometry(int m, int n, int p) {
     g.nw = p / 2 + 1;
     g.me[0] = (m - 1) / 2; g.me[1] = (m - 2) / 2;    // ceil((m-2)/2), floor((m-2)/2)
     g.ne[0] = (n - 1) / 2; g.ne[1] = (n - 2) / 2;
+    for (int par = 0; par < 2; ++par) {
+        g.mp[par] = (g.me[par] + 7) / 8 * 8;
+        g.np[par] = (g.ne[par] + 7) / 8 * 8;
+    }
     for (int w = 0; w < g.nw; ++w) {
         g.plane_w.push_back(w); g.plane_part.push_back(0);
         const bool real_only = (w == 0) || (p % 2 == 0 && w == p / 2);
@@ -397,6 +401,8 @@ Geometry make_geometry(int m, int n, int p) {
     g.nplanes = static_cast<int>(g.plane_w.size());
     g.plane_elems = static_cast<int64_t>(m - 2) * (n - 2);
     g.total_elems = g.plane_elems * g.nplanes;
+    g.eplane_elems = static_cast<int64_t>(g.mp[0] + g.mp[1]) * (g.ne[0] + g.ne[1]);
+    g.etotal_elems = g.eplane_elems * g.nplanes;
     return g;
 }
 
@@ -459,7 +465,8 @@ AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, do
     const Band Bt = band_transpose(z.C02Q), Dt = band_transpose(z.D2Q);
     Band Bp[2], Dp[2];
     for (int par = 0; par < 2; ++par) { Bp[par] = band_parity(Bt, par); Dp[par] = band_parity(Dt, par); }
-    const int me_sum = g.me[0] + g.me[1], ne_sum = g.ne[0] + g.ne[1];
+    // records per shift: both parity blocks, rows padded to a multiple of 8
+    const int me_sum = g.mp[0] + g.mp[1], ne_sum = g.np[0] + g.np[1];
 
     s.J.resize(g.nw); s.bounds.resize(4 * g.nw);
     s.roff.resize(g.nw); s.zoff.resize(g.nw); s.soff.resize(g.nw);
@@ -502,7 +509,7 @@ AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, do
                     rec[8] = dinv[i];
                     rec[9] = Us[3 * i + 0]; rec[10] = Us[3 * i + 1]; rec[11] = Us[3 * i + 2];
                 }
-                base += static_cast<int64_t>(Mu.rows) * kRRec;
+                base += static_cast<int64_t>(g.mp[par]) * kRRec;
             }
             // z-direction records: solve x (v B + D) = z, then w = x (u' B + D)
             base = s.zoff[w] + static_cast<int64_t>(j) * ne_sum * kZRec;
@@ -520,7 +527,7 @@ AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, do
                     if (j + 1 < J)
                         for (int t = 0; t < 4; ++t) rec[4 + t] = Mn.get(k - 1 + t, k);
                 }
-                base += static_cast<int64_t>(N.rows) * kZRec;
+                base += static_cast<int64_t>(g.np[par]) * kZRec;
             }
         }
     }

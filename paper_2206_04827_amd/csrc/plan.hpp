@@ -88,10 +88,14 @@ struct Geometry {
     int nw = 0;                 // floor(p/2) + 1 coefficient slots
     int me[2] = {0, 0};         // r parity block sizes
     int ne[2] = {0, 0};         // z parity block sizes
+    int mp[2] = {0, 0};         // me rounded up to a multiple of 8 (table rows)
+    int np[2] = {0, 0};         // ne rounded up to a multiple of 8
     int nplanes = 0;            // real mode planes (= p)
     std::vector<int> plane_w, plane_part;   // per real plane
-    int64_t plane_elems = 0;    // (m-2)(n-2)
+    int64_t plane_elems = 0;    // (m-2)(n-2): X-layout entries per plane
     int64_t total_elems = 0;    // nplanes * plane_elems
+    int64_t eplane_elems = 0;   // (mp0+mp1)(ne0+ne1): E-layout entries per plane
+    int64_t etotal_elems = 0;   // nplanes * eplane_elems
 };
 Geometry make_geometry(int m, int n, int p);
 
