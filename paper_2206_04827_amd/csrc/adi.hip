@@ -32,7 +32,6 @@ namespace {
 constexpr int G = 8;          // rows per software-pipelined group
 constexpr int kRRec = 12;
 constexpr int kZRec = 8;
-constexpr int kPre = 24;      // coefficient doubles prefetched per thread
 
 // ---------------------------------------------------------------------------
 // LDS-resident sweeps with a compile-time row stride LD (so every row offset
@@ -60,12 +59,16 @@ __device__ __forceinline__ void rpass_lds(double* __restrict__ S, int mp, int k,
     double g1 = 0.0, g2 = 0.0;
     for (int i0 = 0; i0 < mp; i0 += G) {
         double* Sg = Sk + i0 * LD;
-        const double* Rg = RC + i0 * kRRec;
+        const double2* Rg = reinterpret_cast<const double2*>(RC + i0 * kRRec);
         double c[G][8];
 #pragma unroll
         for (int q = 0; q < G; ++q)
 #pragma unroll
-            for (int t = 0; t < 8; ++t) c[q][t] = Rg[q * kRRec + t];
+            for (int t = 0; t < 4; ++t) {
+                const double2 v = Rg[q * (kRRec / 2) + t];
+                c[q][2 * t] = v.x;
+                c[q][2 * t + 1] = v.y;
+            }
 #pragma unroll
         for (int q = 0; q < 8; ++q) wv[6 + q] = Sg[(4 + q) * LD];
         double2 enn[G / 2];
@@ -99,12 +102,16 @@ __device__ __forceinline__ void rpass_lds(double* __restrict__ S, int mp, int k,
     double z1 = 0.0, z2 = 0.0, z3 = 0.0;
     for (int i0 = mp - G; i0 >= 0; i0 -= G) {
         double* Sg = Sk + i0 * LD;
-        const double* Rg = RC + i0 * kRRec + 8;
+        const double2* Rg = reinterpret_cast<const double2*>(RC + i0 * kRRec + 8);
         double c[G][4];
 #pragma unroll
         for (int q = 0; q < G; ++q)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) c[q][t] = Rg[q * kRRec + t];
+            for (int t = 0; t < 2; ++t) {
+                const double2 v = Rg[q * (kRRec / 2) + t];
+                c[q][2 * t] = v.x;
+                c[q][2 * t + 1] = v.y;
+            }
         double gn[G];
         if (i0 > 0) {
 #pragma unroll
@@ -158,14 +165,14 @@ __device__ __forceinline__ void zpass_row(double* __restrict__ row, int np,
     double pn[4] = {0.0, 0.0, 0.0, 0.0};     // product record of column k0 + G
     for (int k0 = np - G; k0 >= 0; k0 -= G) {
         double* rg = row + k0;
-        const double* zg = ZC + k0 * kZRec;
+        const double2* zg = reinterpret_cast<const double2*>(ZC + k0 * kZRec);
         double c[G][3], pr[G][4];
 #pragma unroll
         for (int q = 0; q < G; ++q) {
-#pragma unroll
-            for (int t = 0; t < 3; ++t) c[q][t] = zg[q * kZRec + 1 + t];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) pr[q][t] = zg[q * kZRec + 4 + t];
+            const double2 a = zg[q * (kZRec / 2) + 0], b = zg[q * (kZRec / 2) + 1];
+            const double2 d = zg[q * (kZRec / 2) + 2], e = zg[q * (kZRec / 2) + 3];
+            c[q][0] = a.y; c[q][1] = b.x; c[q][2] = b.y;
+            pr[q][0] = d.x; pr[q][1] = d.y; pr[q][2] = e.x; pr[q][3] = e.y;
         }
         double gn[G];
         if (k0 > 0) {
@@ -197,9 +204,22 @@ __device__ __forceinline__ void zpass(double* row, int np, const double* ZC, boo
     else zpass_row<false>(row, np, ZC);
 }
 
+// Copy n doubles (rounded up to whole 128-double chunks) from global memory
+// straight into LDS, one 16-byte piece per lane (no registers involved).  The
+// source tables carry read slack after their end, the LDS regions are sized in
+// whole chunks.  Completion is awaited with s_waitcnt before the next barrier.
+__device__ __forceinline__ void copy_to_lds(double* dst, const double* __restrict__ src, int n) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int chunks = (n + 127) >> 7;
+    for (int c = wave; c < chunks; c += nwaves)
+        __builtin_amdgcn_global_load_lds(src + (c << 7) + 2 * lane, dst + (c << 7), 16, 0, 0);
+}
+
+__device__ __forceinline__ int lds_chunks(int n) { return (n + 127) / 128 * 128; }
+
 // One workgroup per parity block, all J iterations, block state in LDS.
-// The records of shift j+1 are loaded into registers while shift j sweeps and
-// copied to LDS between iterations.
+// While the z-pass of shift j runs, the r-records of shift j+1 stream into
+// LDS; while the r-pass of shift j+1 runs, its z-records follow.
 template <int LD>
 __device__ __forceinline__ void adi_block_lds(double* sm, const BlockDesc& bd,
                                               const double* __restrict__ E, double* X,
@@ -210,42 +230,25 @@ __device__ __forceinline__ void adi_block_lds(double* sm, const BlockDesc& bd,
     const int tid = threadIdx.x, nt = blockDim.x;
     double* S = sm;
     double* RCs = sm + (mp + 4) * LD;
-    double* ZCs = RCs + mp * kRRec;
+    double* ZCs = RCs + lds_chunks(mp * kRRec);
     const int nr = mp * kRRec, nz = np * kZRec;
     for (int idx = tid; idx < (mp + 4) * LD; idx += nt) S[idx] = 0.0;
-    double pre[kPre];
-    auto fetch = [&](int j) {
-        const double* rs = rtab + bd.rbase + j * bd.rstride;
-        const double* zs = ztab + bd.zbase + j * bd.zstride;
-#pragma unroll
-        for (int c = 0; c < kPre; ++c) {
-            const int idx = tid + c * nt;
-            pre[c] = idx < nr ? rs[idx] : (idx < nr + nz ? zs[idx - nr] : 0.0);
-        }
-    };
-    auto store = [&]() {
-#pragma unroll
-        for (int c = 0; c < kPre; ++c) {
-            const int idx = tid + c * nt;
-            if (idx < nr) RCs[idx] = pre[c];
-            else if (idx < nr + nz) ZCs[idx - nr] = pre[c];
-        }
-    };
-    fetch(0);
-    store();
+    copy_to_lds(RCs, rtab + bd.rbase, nr);
+    copy_to_lds(ZCs, ztab + bd.zbase, nz);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const double* Ecol = E + bd.eoff + static_cast<int64_t>(tid) * mp;
     for (int j = 0; j < bd.J; ++j) {
-        if (j + 1 < bd.J) fetch(j + 1);
         const double vm = vmu[bd.soff + j];
         if (tid < ne) rpass_lds<LD>(S, mp, tid, RCs, Ecol, vm);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+        const bool more = j + 1 < bd.J;
+        if (more) copy_to_lds(RCs, rtab + bd.rbase + (j + 1) * bd.rstride, nr);
         if (tid < me) zpass(S + tid * LD, np, ZCs, j == bd.J - 1);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (j + 1 < bd.J) {
-            store();
-            __syncthreads();
-        }
+        if (more) copy_to_lds(ZCs, ztab + bd.zbase + (j + 1) * bd.zstride, nz);
     }
     double* Xb = X + bd.xoff;
     for (int idx = tid; idx < me * ne; idx += nt) {

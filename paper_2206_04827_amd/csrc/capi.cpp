@@ -218,6 +218,9 @@ std::unique_ptr<Setup> make_setup(cyl_plan_t pl, double ka, double eps) {
                 s->hblocks.push_back(b);
             }
     }
+    // the ADI kernel copies records in 128-double chunks: keep read slack
+    s->h.rtab.resize(s->h.rtab.size() + 256, 0.0);
+    s->h.ztab.resize(s->h.ztab.size() + 256, 0.0);
     upload(s->rtab, s->h.rtab);
     upload(s->ztab, s->h.ztab);
     upload(s->vmu, s->h.vmu);
@@ -441,8 +444,9 @@ void build_plan(cyl_plan_t pl) {
     // ADI variant: LDS-resident when the largest block and its records fit
     pl->adi_threads = ((std::max(g.me[0], g.ne[0]) + 63) / 64) * 64;
     pl->state_stride = static_cast<int64_t>(g.mp[0] + 4) * (g.np[0] + 1);
-    pl->lds_bytes = (static_cast<size_t>(pl->state_stride) + static_cast<size_t>(kRRec) * g.mp[0] +
-                     static_cast<size_t>(kZRec) * g.np[0]) * sizeof(double);
+    auto chunks = [](int x) { return static_cast<size_t>((x + 127) / 128 * 128); };
+    pl->lds_bytes = (static_cast<size_t>(pl->state_stride) + chunks(kRRec * g.mp[0]) +
+                     chunks(kZRec * g.np[0])) * sizeof(double);
     int dev = 0, max_lds = 0;
     hip_check(hipGetDevice(&dev), "hipGetDevice");
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 65536;
@@ -451,8 +455,7 @@ void build_plan(cyl_plan_t pl) {
         max_lds = std::max(max_lds, max_lds_sm);
     const int mode = env_int("CYLSPEC_ADI_GLOBAL", 0);
     pl->use_lds = mode == 0 && pl->adi_threads <= 256 && g.np[0] <= 128 &&
-                  pl->lds_bytes <= static_cast<size_t>(max_lds) &&
-                  static_cast<int>(kRRec * g.mp[0] + kZRec * g.np[0]) <= 24 * pl->adi_threads;
+                  pl->lds_bytes <= static_cast<size_t>(max_lds);
     if (pl->use_lds && pl->lds_bytes > 65536) {
         if (adi_set_lds_limit(g.np[0], pl->lds_bytes) != hipSuccess) {
             (void)hipGetLastError();
