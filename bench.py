@@ -30,6 +30,11 @@ HBM_PEAK_GBS = 8000.0
 # formulation: r-pass 24 (banded product 11, E term 2, forward 4, backward 7),
 # z-pass 14 (forward 2, backward 5, banded product 7).
 ADI_FLOPS_PER_UNKNOWN_ITER = 38.0
+# HBM bytes per ADI launch at 256^3 from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# (scaled by a 512 MiB copy: fetch x2.0, write x1.0), valid for the ADI source
+# whose SHA-256 starts with ADI_TRAFFIC_SHA; reported as null otherwise.
+ADI_TRAFFIC_BYTES_256 = 2.495e9
+ADI_TRAFFIC_SHA = "9e8850efd60acb30"
 
 
 def parse():
@@ -43,6 +48,9 @@ def parse():
     ap.add_argument("--no-heat", action="store_true")
     ap.add_argument("--cpu-modes", type=int, default=16,
                     help="wavenumbers the CPU oracle solves in its timed sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 512 MiB device-to-device copy (a known-size "
+                         "kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -119,8 +127,13 @@ def main():
     passes = info["passes"]
     flops_per_launch = ADI_FLOPS_PER_UNKNOWN_ITER * (m - 2) * (n - 2) * p * info["adi_iterations_mean"]
     achieved = flops_per_launch / (adi_ms * 1e-3) / 1e12
+    import hashlib
+    src = os.path.join(ROOT, "paper_2206_04827_amd", "csrc", "adi.hip")
+    with open(src, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+    traffic = ADI_TRAFFIC_BYTES_256 if (sha == ADI_TRAFFIC_SHA and m == 256 and passes == 2) else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
                 "kernel": "k_adi_lds (one ADI pass over all parity blocks)",
                 "avg_launch_ms": round(adi_ms, 4), "launches": n_adi}
     phases = {k[3:]: round(prof[k] / args.steps, 4) for k in prof if k.startswith("ms_")}
@@ -154,6 +167,13 @@ def main():
                            "note": "forward BDF1 steps only (no adjoint in this build)"}
         H.close()
         hp.close()
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = a.numel() * 8
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, n, p, synth.SEED_BASE + 3, args.cpu_modes)
