@@ -10,7 +10,7 @@ namespace cyl {
 // a power-of-two FFT of length Nb, directly (L == Nb) or by Bluestein.
 struct DftDev {
     int L, Nb, log2Nb, bluestein;
-    const double2* tw;      // Nb twiddles exp(-2 pi i k / Nb)
+    const double2* tw;      // Nb: per-pass twiddles of the Stockham FFT
     const double2* chirp;   // L   (Bluestein only)
     const double2* bhat;    // Nb  (Bluestein only)
 };

@@ -581,11 +581,26 @@ DftTables build_dft_tables(int L) {
     else while (Nb < 2 * L - 1) Nb <<= 1;
     t.Nb = Nb;
     while ((1 << t.log2Nb) < Nb) ++t.log2Nb;
-    t.tw.resize(2 * static_cast<size_t>(Nb));
-    for (int k = 0; k < Nb; ++k) {
-        const long double ang = -2.0L * pi * k / Nb;
-        t.tw[2 * k] = static_cast<double>(std::cos(ang));
-        t.tw[2 * k + 1] = static_cast<double>(std::sin(ang));
+    // Per-pass twiddles of the radix-16/8/4/2 Stockham FFT, in pass order:
+    // for the pass of radix R on sub-transforms of length Ls, entries
+    // [k (R-1) + q - 1] = exp(-2 pi i k q / (R Ls)), k < Ls, 1 <= q < R
+    // (N - 1 entries in total; the table is padded to Nb).
+    t.tw.assign(2 * static_cast<size_t>(Nb), 0.0);
+    {
+        size_t off = 0;
+        for (int Ls = 1; Ls < Nb;) {
+            const int rem = Nb / Ls;
+            const int R = rem >= 16 ? 16 : rem;
+            for (int k = 0; k < Ls; ++k)
+                for (int q = 1; q < R; ++q) {
+                    const long double ang = -2.0L * pi * static_cast<long double>(k) * q /
+                                            (static_cast<long double>(R) * Ls);
+                    t.tw[2 * off] = static_cast<double>(std::cos(ang));
+                    t.tw[2 * off + 1] = static_cast<double>(std::sin(ang));
+                    ++off;
+                }
+            Ls *= R;
+        }
     }
     if (t.bluestein) {
         t.chirp.resize(2 * static_cast<size_t>(L));

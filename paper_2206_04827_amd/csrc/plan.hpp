@@ -59,7 +59,7 @@ double ellip_K_from_kp(double kp);
 struct DftTables {
     int L = 0, Nb = 0, log2Nb = 0;
     bool bluestein = false;
-    std::vector<double> tw;     // 2*Nb: exp(-2 pi i k / Nb)
+    std::vector<double> tw;     // 2*Nb: per-pass FFT twiddles (see build_dft_tables)
     std::vector<double> chirp;  // 2*L : exp(-i pi n^2 / L)
     std::vector<double> bhat;   // 2*Nb: FFT of the Bluestein filter, times 1/Nb
 };

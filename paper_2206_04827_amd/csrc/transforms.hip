@@ -6,113 +6,219 @@
 // r, z : DCT-I of length M + 1 as the length-2M DFT of the even extension;
 //        complex lines carry the DCT of their real and imaginary parts at
 //        once.
-// Every DFT is a power-of-two Stockham FFT (radix 4, one radix-2 stage when
-// log2 N is odd) in LDS; other lengths go through Bluestein's chirp-z
-// identity with a power-of-two convolution.
+// Every DFT is a power-of-two Stockham FFT in LDS made of radix-16/8/4/2
+// passes whose butterflies run in registers; the twiddle table is staged in
+// LDS once per workgroup.  Lengths that are not powers of two go through
+// Bluestein's chirp-z identity with a power-of-two convolution.
 #include "kernels.hpp"
 
 namespace cyl {
 namespace {
 
-constexpr int kThreads = 256;
-
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// multiply by -i
+__device__ __forceinline__ double2 cmi(double2 a) { return make_double2(a.y, -a.x); }
 
-// In-place forward FFT (sign -1) of one line of length N (power of two) held
-// in LDS, by TPL cooperating threads (t = 0..TPL-1).  Every thread of the
-// workgroup must call it (it contains barriers).  Each radix-4 stage reads
-// all inputs to registers, synchronises, then writes: one buffer suffices.
-__device__ void fft_lds(double2* buf, int N, const double2* __restrict__ tw, int t, int TPL) {
-    int Ls = 1;
-    while (4 * Ls <= N) {
-        const int nb = N >> 2;
-        const int tstride = N / (4 * Ls);
-        double2 y0[4], y1[4], y2[4], y3[4];
-        int ob[4];
+// ---------------------------------------------------------------------------
+// in-register DFTs (forward, exp(-2 pi i j k / R))
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void dft2(double2& a, double2& b) {
+    const double2 t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+__device__ __forceinline__ void dft4(double2& x0, double2& x1, double2& x2, double2& x3) {
+    const double2 a0 = cadd(x0, x2), a1 = csub(x0, x2), a2 = cadd(x1, x3), a3 = cmi(csub(x1, x3));
+    x0 = cadd(a0, a2);
+    x2 = csub(a0, a2);
+    x1 = cadd(a1, a3);
+    x3 = csub(a1, a3);
+}
+
+// cos and sin of 2 pi k / 16 for k = 0..9 (exp(-2 pi i k / 16) = (C - i S))
+__constant__ double kC16[10] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                                0.38268343236508977173, 0.0, -0.38268343236508977173,
+                                -0.70710678118654752440, -0.92387953251128675613, -1.0,
+                                -0.92387953251128675613};
+__constant__ double kS16[10] = {0.0, 0.38268343236508977173, 0.70710678118654752440,
+                                0.92387953251128675613, 1.0, 0.92387953251128675613,
+                                0.70710678118654752440, 0.38268343236508977173, 0.0,
+                                -0.38268343236508977173};
+
+template <int R>
+__device__ __forceinline__ void dft_reg(double2* x);
+
+template <>
+__device__ __forceinline__ void dft_reg<1>(double2*) {}
+template <>
+__device__ __forceinline__ void dft_reg<2>(double2* x) { dft2(x[0], x[1]); }
+template <>
+__device__ __forceinline__ void dft_reg<4>(double2* x) { dft4(x[0], x[1], x[2], x[3]); }
+
+// 8 = 4 x 2: DFT-4 over even/odd halves, twiddles exp(-2 pi i k / 8), DFT-2.
+template <>
+__device__ __forceinline__ void dft_reg<8>(double2* x) {
+    double2 e[4] = {x[0], x[2], x[4], x[6]}, o[4] = {x[1], x[3], x[5], x[7]};
+    dft4(e[0], e[1], e[2], e[3]);
+    dft4(o[0], o[1], o[2], o[3]);
+    const double h = 0.70710678118654752440;
+    o[1] = make_double2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));     // * (1 - i)/sqrt2
+    o[2] = cmi(o[2]);
+    o[3] = make_double2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));    // * (-1 - i)/sqrt2
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int b = t + c * TPL;
-            ob[c] = -1;
-            if (b < nb) {
-                const int k = b & (Ls - 1);
-                double2 x0 = buf[b], x1 = buf[b + nb], x2 = buf[b + 2 * nb], x3 = buf[b + 3 * nb];
-                if (Ls > 1) {
-                    const int e = k * tstride;
-                    x1 = cmul(x1, tw[e]);
-                    x2 = cmul(x2, tw[2 * e]);
-                    x3 = cmul(x3, tw[3 * e]);
-                }
-                const double2 a0 = make_double2(x0.x + x2.x, x0.y + x2.y);
-                const double2 a1 = make_double2(x0.x - x2.x, x0.y - x2.y);
-                const double2 a2 = make_double2(x1.x + x3.x, x1.y + x3.y);
-                const double2 a3 = make_double2(x1.x - x3.x, x1.y - x3.y);
-                // (-i) * a3 = (a3.y, -a3.x)
-                y0[c] = make_double2(a0.x + a2.x, a0.y + a2.y);
-                y2[c] = make_double2(a0.x - a2.x, a0.y - a2.y);
-                y1[c] = make_double2(a1.x + a3.y, a1.y - a3.x);
-                y3[c] = make_double2(a1.x - a3.y, a1.y + a3.x);
-                ob[c] = ((b - k) << 2) + k;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (ob[c] >= 0) {
-                buf[ob[c]] = y0[c];
-                buf[ob[c] + Ls] = y1[c];
-                buf[ob[c] + 2 * Ls] = y2[c];
-                buf[ob[c] + 3 * Ls] = y3[c];
-            }
-        }
-        __syncthreads();
-        Ls <<= 2;
+    for (int k = 0; k < 4; ++k) {
+        x[k] = cadd(e[k], o[k]);
+        x[k + 4] = csub(e[k], o[k]);
     }
-    if (Ls < N) {  // final radix-2 stage, Ls = N / 2
-        const int nb = N >> 1;
-        double2 y0[8], y1[8];
-        int ob[8];
+}
+
+// 16 = 4 x 4 Cooley-Tukey with twiddles exp(-2 pi i j k / 16).
+template <>
+__device__ __forceinline__ void dft_reg<16>(double2* x) {
+    double2 y[4][4];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int b = t + c * TPL;
-            ob[c] = -1;
-            if (b < nb) {
-                const double2 x0 = buf[b];
-                const double2 x1 = cmul(buf[b + nb], tw[b]);
-                y0[c] = make_double2(x0.x + x1.x, x0.y + x1.y);
-                y1[c] = make_double2(x0.x - x1.x, x0.y - x1.y);
-                ob[c] = b;
-            }
-        }
-        __syncthreads();
+    for (int j = 0; j < 4; ++j) {
+        y[j][0] = x[j]; y[j][1] = x[j + 4]; y[j][2] = x[j + 8]; y[j][3] = x[j + 12];
+        dft4(y[j][0], y[j][1], y[j][2], y[j][3]);
+    }
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            if (ob[c] >= 0) {
-                buf[ob[c]] = y0[c];
-                buf[ob[c] + Ls] = y1[c];
-            }
+    for (int j = 1; j < 4; ++j)
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            const int e = j * k;
+            y[j][k] = cmul(y[j][k], make_double2(kC16[e], -kS16[e]));
         }
-        __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double2 a = y[0][k], b = y[1][k], c = y[2][k], d = y[3][k];
+        dft4(a, b, c, d);
+        x[k] = a; x[k + 4] = b; x[k + 8] = c; x[k + 12] = d;
+    }
+}
+
+// Line buffers in LDS skip one slot after every 16 points, so that the
+// stride-16 writes of a radix-16 pass fall in distinct banks.
+__device__ __forceinline__ int P(int i) { return i + (i >> 4); }
+
+// One Stockham pass of radix R over a line of N points in LDS, already
+// combined into sub-transforms of length Ls: butterfly b reads x[b + q N/R],
+// scales input q by exp(-2 pi i k q / (R Ls)) (k = b mod Ls), and writes
+// output r to (b - k) R + k + r Ls.  Each thread holds 16 points.  The
+// pass's twiddles are stored as tw[k (R-1) + q - 1].
+template <int R>
+__device__ __forceinline__ void fft_pass(double2* buf, int N, int Ls, const double2* tw, int t, int T) {
+    constexpr int B = 16 / R;
+    const int nb = N / R;
+    double2 x[B][R];
+    int ob[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+        const int b = t + c * T;
+        ob[c] = -1;
+        if (b < nb) {
+            const int k = b & (Ls - 1);
+#pragma unroll
+            for (int q = 0; q < R; ++q) x[c][q] = buf[P(b + q * nb)];
+            if (Ls > 1) {
+                const double2* tk = tw + k * (R - 1) - 1;
+#pragma unroll
+                for (int q = 1; q < R; ++q) x[c][q] = cmul(x[c][q], tk[q]);
+            }
+            dft_reg<R>(x[c]);
+            ob[c] = (b - k) * R + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+        if (ob[c] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[P(ob[c] + r * Ls)] = x[c][r];
+        }
+    }
+    __syncthreads();
+}
+
+// In-place forward FFT of a power-of-two line in LDS (all threads of the
+// workgroup must call it: it contains barriers).  tw: the per-pass twiddle
+// tables, concatenated in pass order (N - 1 entries).
+__device__ __forceinline__ void fft_lds(double2* buf, int N, const double2* tw, int t, int T) {
+    int Ls = 1;
+    while (Ls < N) {
+        const int rem = N / Ls;
+        if (rem >= 16) { fft_pass<16>(buf, N, Ls, tw, t, T); tw += Ls * 15; Ls *= 16; }
+        else if (rem == 8) { fft_pass<8>(buf, N, Ls, tw, t, T); tw += Ls * 7; Ls *= 8; }
+        else if (rem == 4) { fft_pass<4>(buf, N, Ls, tw, t, T); tw += Ls * 3; Ls *= 4; }
+        else { fft_pass<2>(buf, N, Ls, tw, t, T); tw += Ls; Ls *= 2; }
     }
 }
 
 // DFT of the length-L line held (pre-multiplied by the chirp when Bluestein)
 // in buf[0..Nb); leaves X_k, k < L, in buf[0..L).
-__device__ void dft_lds(double2* buf, const DftDev& d, int t, int TPL) {
-    fft_lds(buf, d.Nb, d.tw, t, TPL);
+// Every thread owns at most kPts = 16 points of a line (T = Nb / 16 threads
+// per line), so the pointwise loops below have a fixed trip count and issue
+// all of their table loads before the first use.
+constexpr int kPts = 16;
+
+__device__ __forceinline__ void dft_lds(double2* buf, const DftDev& d, const double2* tw, int t, int T) {
+    fft_lds(buf, d.Nb, tw, t, T);
     if (d.bluestein) {
-        for (int k = t; k < d.Nb; k += TPL) buf[k] = cconj(cmul(buf[k], d.bhat[k]));
+        double2 bh[kPts];
+#pragma unroll
+        for (int c = 0; c < kPts; ++c) {
+            const int k = t + c * T;
+            bh[c] = k < d.Nb ? d.bhat[k] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int c = 0; c < kPts; ++c) {
+            const int k = t + c * T;
+            if (k < d.Nb) buf[P(k)] = cconj(cmul(buf[P(k)], bh[c]));
+        }
         __syncthreads();
-        fft_lds(buf, d.Nb, d.tw, t, TPL);
-        for (int k = t; k < d.L; k += TPL) buf[k] = cmul(cconj(buf[k]), d.chirp[k]);
+        fft_lds(buf, d.Nb, tw, t, T);
+#pragma unroll
+        for (int c = 0; c < kPts; ++c) {
+            const int k = t + c * T;
+            bh[c] = k < d.L ? d.chirp[k] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int c = 0; c < kPts; ++c) {
+            const int k = t + c * T;
+            if (k < d.L) buf[P(k)] = cmul(cconj(buf[P(k)]), bh[c]);
+        }
         __syncthreads();
     }
 }
 
+// Padded line length in LDS (odd, so that lines in neighbouring lanes fall in
+// distinct banks).
+__host__ __device__ __forceinline__ int line_stride(int Nb) { return Nb + (Nb >> 4) + 1; }
+
 __device__ __forceinline__ double2 load_chirped(double2 v, const DftDev& d, int n) {
     return d.bluestein ? cmul(v, d.chirp[n]) : v;
+}
+
+// Stage the twiddle table in LDS (shared by every line of the workgroup).
+__device__ __forceinline__ void stage_twiddles(double2* tws, const DftDev& d) {
+    for (int k0 = 0; k0 < d.Nb; k0 += 4 * blockDim.x) {
+        double2 v[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int k = k0 + threadIdx.x + c * blockDim.x;
+            v[c] = k < d.Nb ? d.tw[k] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int k = k0 + threadIdx.x + c * blockDim.x;
+            if (k < d.Nb) tws[k] = v[c];
+        }
+    }
 }
 
 template <bool kLineFast>
@@ -121,12 +227,14 @@ __device__ __forceinline__ void line_thread(int LPW, int TPL, int* li, int* t) {
     else           { *li = threadIdx.x / TPL; *t = threadIdx.x % TPL; }
 }
 
+// LDS: [twiddles: Nb][line 0: line_stride(Nb)][line 1] ...
 template <bool kLineFast>
-__global__ __launch_bounds__(kThreads) void k_dct(const double2* in, double2* out, LineSet ls,
-                                                  int mlen, DftDev d,
-                                                  const double* __restrict__ pre,
-                                                  const double* __restrict__ post, int TPL, int LPW) {
+__global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, LineSet ls,
+                                              int mlen, DftDev d,
+                                              const double* __restrict__ pre,
+                                              const double* __restrict__ post, int TPL, int LPW) {
     extern __shared__ double2 lds[];
+    double2* tws = lds;
     int li, t;
     line_thread<kLineFast>(LPW, TPL, &li, &t);
     const int64_t line = static_cast<int64_t>(blockIdx.x) * LPW + li;
@@ -134,36 +242,60 @@ __global__ __launch_bounds__(kThreads) void k_dct(const double2* in, double2* ou
     const bool valid = line < nlines;
     int64_t base = 0;
     if (valid) base = (line / ls.n_inner) * ls.outer + (line % ls.n_inner) * ls.inner;
-    double2* buf = lds + li * (d.Nb + 1);
+    double2* buf = lds + d.Nb + li * line_stride(d.Nb);
+    stage_twiddles(tws, d);
     const int M = mlen - 1, L = 2 * M;
-    for (int s = t; s <= M; s += TPL) {
-        double2 v = make_double2(0.0, 0.0);
-        if (valid) {
-            v = in[base + s * ls.elem];
-            const double ps = pre[s];
-            v.x *= ps; v.y *= ps;
+    // the line has M + 1 <= Nb / 2 + 1 points: at most kPts / 2 + 1 per thread
+    constexpr int kIn = kPts / 2 + 1;
+    double2 v[kIn], ca[kIn], cb[kIn];
+    double ps[kIn];
+#pragma unroll
+    for (int c = 0; c < kIn; ++c) {
+        const int s = t + c * TPL;
+        const bool ok = s <= M;
+        v[c] = (ok && valid) ? in[base + s * ls.elem] : make_double2(0.0, 0.0);
+        ps[c] = ok ? pre[s] : 0.0;
+        if (d.bluestein) {
+            ca[c] = ok ? d.chirp[s] : make_double2(0.0, 0.0);
+            cb[c] = (ok && s >= 1 && s < M) ? d.chirp[L - s] : make_double2(0.0, 0.0);
         }
-        buf[s] = load_chirped(v, d, s);
-        if (s >= 1 && s < M) buf[L - s] = load_chirped(v, d, L - s);
     }
-    for (int s = L + t; s < d.Nb; s += TPL) buf[s] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < kIn; ++c) {
+        const int s = t + c * TPL;
+        if (s <= M) {
+            const double2 x = make_double2(v[c].x * ps[c], v[c].y * ps[c]);
+            buf[P(s)] = d.bluestein ? cmul(x, ca[c]) : x;
+            if (s >= 1 && s < M) buf[P(L - s)] = d.bluestein ? cmul(x, cb[c]) : x;
+        }
+    }
+    for (int s = L + t; s < d.Nb; s += TPL) buf[P(s)] = make_double2(0.0, 0.0);
     __syncthreads();
-    dft_lds(buf, d, t, TPL);
+    dft_lds(buf, d, tws, t, TPL);
     if (valid) {
-        for (int k = t; k <= M; k += TPL) {
-            const double2 X = buf[k];
-            const double ps = post[k];
-            out[base + k * ls.elem] = make_double2(X.x * ps, X.y * ps);
+#pragma unroll
+        for (int c = 0; c < kIn; ++c) {
+            const int k = t + c * TPL;
+            ps[c] = k <= M ? post[k] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < kIn; ++c) {
+            const int k = t + c * TPL;
+            if (k <= M) {
+                const double2 X = buf[P(k)];
+                out[base + k * ls.elem] = make_double2(X.x * ps[c], X.y * ps[c]);
+            }
         }
     }
 }
 
 // values [p][n][m] (real) -> planes [p/2+1][n][m] (complex): theta DFT with the
 // (-1)^w phase of theta_0 = -pi and the 1/p normalisation.
-__global__ __launch_bounds__(kThreads) void k_theta_fwd(const double* __restrict__ val,
-                                                        double2* __restrict__ planes, int m,
-                                                        int n, int p, DftDev d, int TPL, int LPW) {
+__global__ __launch_bounds__(512) void k_theta_fwd(const double* __restrict__ val,
+                                                    double2* __restrict__ planes, int m, int n,
+                                                    int p, DftDev d, int TPL, int LPW) {
     extern __shared__ double2 lds[];
+    double2* tws = lds;
     int li, t;
     line_thread<true>(LPW, TPL, &li, &t);
     const int hm = (m + 1) / 2;
@@ -172,21 +304,22 @@ __global__ __launch_bounds__(kThreads) void k_theta_fwd(const double* __restrict
     const int k = valid ? static_cast<int>(pair / hm) : 0;
     const int j0 = valid ? 2 * static_cast<int>(pair % hm) : 0;
     const bool has1 = valid && (j0 + 1 < m);
-    double2* buf = lds + li * (d.Nb + 1);
+    double2* buf = lds + d.Nb + li * line_stride(d.Nb);
+    stage_twiddles(tws, d);
     for (int l = t; l < p; l += TPL) {
         const int64_t off = (static_cast<int64_t>(l) * n + k) * m + j0;
         const double a = valid ? val[off] : 0.0;
         const double b = has1 ? val[off + 1] : 0.0;
-        buf[l] = load_chirped(make_double2(a, b), d, l);
+        buf[P(l)] = load_chirped(make_double2(a, b), d, l);
     }
-    for (int l = p + t; l < d.Nb; l += TPL) buf[l] = make_double2(0.0, 0.0);
+    for (int l = p + t; l < d.Nb; l += TPL) buf[P(l)] = make_double2(0.0, 0.0);
     __syncthreads();
-    dft_lds(buf, d, t, TPL);
+    dft_lds(buf, d, tws, t, TPL);
     const int nw = p / 2 + 1;
     const double invp = 1.0 / p;
     for (int w = t; w < nw; w += TPL) {
-        const double2 Zw = buf[w];
-        const double2 Zm = buf[(p - w) % p];
+        const double2 Zw = buf[P(w)];
+        const double2 Zm = buf[P((p - w) % p)];
         const double sc = (w & 1) ? -invp : invp;
         double2 A = make_double2(0.5 * (Zw.x + Zm.x) * sc, 0.5 * (Zw.y - Zm.y) * sc);
         double2 B = make_double2(0.5 * (Zw.y + Zm.y) * sc, -0.5 * (Zw.x - Zm.x) * sc);
@@ -199,10 +332,11 @@ __global__ __launch_bounds__(kThreads) void k_theta_fwd(const double* __restrict
 
 // planes -> values: f_l = sum_w Y_w e^{+2 pi i w l / p}, Y_w = (-1)^w c_w and
 // its Hermitian extension; two r-lines per complex inverse DFT.
-__global__ __launch_bounds__(kThreads) void k_theta_inv(const double2* __restrict__ planes,
-                                                        double* __restrict__ val, int m, int n,
-                                                        int p, DftDev d, int TPL, int LPW) {
+__global__ __launch_bounds__(512) void k_theta_inv(const double2* __restrict__ planes,
+                                                    double* __restrict__ val, int m, int n, int p,
+                                                    DftDev d, int TPL, int LPW) {
     extern __shared__ double2 lds[];
+    double2* tws = lds;
     int li, t;
     line_thread<true>(LPW, TPL, &li, &t);
     const int hm = (m + 1) / 2;
@@ -211,7 +345,8 @@ __global__ __launch_bounds__(kThreads) void k_theta_inv(const double2* __restric
     const int k = valid ? static_cast<int>(pair / hm) : 0;
     const int j0 = valid ? 2 * static_cast<int>(pair % hm) : 0;
     const bool has1 = valid && (j0 + 1 < m);
-    double2* buf = lds + li * (d.Nb + 1);
+    double2* buf = lds + d.Nb + li * line_stride(d.Nb);
+    stage_twiddles(tws, d);
     for (int l = t; l < p; l += TPL) {
         const int wq = (2 * l <= p) ? l : p - l;
         const bool cj = 2 * l > p;
@@ -223,62 +358,88 @@ __global__ __launch_bounds__(kThreads) void k_theta_inv(const double2* __restric
         if (cj) { ca.y = -ca.y; cb.y = -cb.y; }
         // Z = Ya + i Yb; the inverse DFT is conj(DFT(conj(Z)))
         const double2 Z = make_double2(sg * (ca.x - cb.y), sg * (ca.y + cb.x));
-        buf[l] = load_chirped(cconj(Z), d, l);
+        buf[P(l)] = load_chirped(cconj(Z), d, l);
     }
-    for (int l = p + t; l < d.Nb; l += TPL) buf[l] = make_double2(0.0, 0.0);
+    for (int l = p + t; l < d.Nb; l += TPL) buf[P(l)] = make_double2(0.0, 0.0);
     __syncthreads();
-    dft_lds(buf, d, t, TPL);
+    dft_lds(buf, d, tws, t, TPL);
     for (int l = t; l < p; l += TPL) {
-        const double2 z = cconj(buf[l]);
+        const double2 z = cconj(buf[P(l)]);
         const int64_t off = (static_cast<int64_t>(l) * n + k) * m + j0;
         if (valid) val[off] = z.x;
         if (has1) val[off + 1] = z.y;
     }
 }
 
-void line_config(int Nb, int* TPL, int* LPW, size_t* lds) {
+// Threads per line: one radix-16 butterfly each in the widest pass.  Lines
+// per workgroup: strided lines take as many lines as keep ~128 KB of data in
+// LDS (full 128-byte segments per element index), contiguous lines fill 256
+// threads.
+void line_config(int Nb, bool strided, int* TPL, int* LPW, int* threads, size_t* lds) {
     *TPL = Nb >= 16 ? Nb / 16 : 1;
-    if (*TPL > kThreads) *TPL = kThreads;
-    *LPW = kThreads / *TPL;
-    *lds = static_cast<size_t>(*LPW) * (Nb + 1) * sizeof(double2);
+    int l;
+    if (strided) {
+        l = static_cast<int>(131072 / (static_cast<size_t>(line_stride(Nb)) * sizeof(double2)));
+        if (l > 16) l = 16;
+        if (l * *TPL < 64) l = (64 + *TPL - 1) / *TPL;
+        if (l * *TPL > 512) l = 512 / *TPL;
+    } else {
+        l = *TPL >= 256 ? 1 : 256 / *TPL;
+    }
+    if (l < 1) l = 1;
+    *LPW = l;
+    *threads = l * *TPL;           // exactly LPW lines x TPL threads
+    *lds = (static_cast<size_t>(*LPW) * line_stride(Nb) + Nb) * sizeof(double2);
+}
+
+template <typename K>
+void raise_lds(K kernel, size_t bytes) {
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
 
 }  // namespace
 
 hipError_t launch_theta_fwd(const double* values, double2* planes, int m, int n, int p,
                             const DftDev& d, hipStream_t s) {
-    int TPL, LPW;
+    int TPL, LPW, threads;
     size_t lds;
-    line_config(d.Nb, &TPL, &LPW, &lds);
+    line_config(d.Nb, true, &TPL, &LPW, &threads, &lds);
+    raise_lds(k_theta_fwd, lds);
     const int64_t lines = static_cast<int64_t>(n) * ((m + 1) / 2);
     const unsigned grid = static_cast<unsigned>((lines + LPW - 1) / LPW);
-    hipLaunchKernelGGL(k_theta_fwd, dim3(grid), dim3(kThreads), lds, s, values, planes, m, n, p, d, TPL, LPW);
+    hipLaunchKernelGGL(k_theta_fwd, dim3(grid), dim3(threads), lds, s, values, planes, m, n, p, d, TPL, LPW);
     return hipGetLastError();
 }
 
 hipError_t launch_theta_inv(const double2* planes, double* values, int m, int n, int p,
                             const DftDev& d, hipStream_t s) {
-    int TPL, LPW;
+    int TPL, LPW, threads;
     size_t lds;
-    line_config(d.Nb, &TPL, &LPW, &lds);
+    line_config(d.Nb, true, &TPL, &LPW, &threads, &lds);
+    raise_lds(k_theta_inv, lds);
     const int64_t lines = static_cast<int64_t>(n) * ((m + 1) / 2);
     const unsigned grid = static_cast<unsigned>((lines + LPW - 1) / LPW);
-    hipLaunchKernelGGL(k_theta_inv, dim3(grid), dim3(kThreads), lds, s, planes, values, m, n, p, d, TPL, LPW);
+    hipLaunchKernelGGL(k_theta_inv, dim3(grid), dim3(threads), lds, s, planes, values, m, n, p, d, TPL, LPW);
     return hipGetLastError();
 }
 
 hipError_t launch_dct(const double2* in, double2* out, const LineSet& ls, int mlen,
                       bool contiguous_lines, const DftDev& d, const double* pre,
                       const double* post, hipStream_t s) {
-    int TPL, LPW;
+    int TPL, LPW, threads;
     size_t lds;
-    line_config(d.Nb, &TPL, &LPW, &lds);
+    line_config(d.Nb, !contiguous_lines, &TPL, &LPW, &threads, &lds);
     const int64_t lines = static_cast<int64_t>(ls.n_outer) * ls.n_inner;
     const unsigned grid = static_cast<unsigned>((lines + LPW - 1) / LPW);
-    if (contiguous_lines)
-        hipLaunchKernelGGL(k_dct<false>, dim3(grid), dim3(kThreads), lds, s, in, out, ls, mlen, d, pre, post, TPL, LPW);
-    else
-        hipLaunchKernelGGL(k_dct<true>, dim3(grid), dim3(kThreads), lds, s, in, out, ls, mlen, d, pre, post, TPL, LPW);
+    if (contiguous_lines) {
+        raise_lds(k_dct<false>, lds);
+        hipLaunchKernelGGL(k_dct<false>, dim3(grid), dim3(threads), lds, s, in, out, ls, mlen, d, pre, post, TPL, LPW);
+    } else {
+        raise_lds(k_dct<true>, lds);
+        hipLaunchKernelGGL(k_dct<true>, dim3(grid), dim3(threads), lds, s, in, out, ls, mlen, d, pre, post, TPL, LPW);
+    }
     return hipGetLastError();
 }
 
