@@ -28,4 +28,4 @@ Readings of places where the paper is silent, garbled or inconsistent are
 stated where they are used.
 """
 
-from . import operators, transforms, sylvester, adi, problems  # noqa: F401
+from . import operators, transforms, sylvester, adi, problems, adjoint  # noqa: F401
