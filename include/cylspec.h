@@ -44,6 +44,7 @@ extern "C" {
 
 typedef struct cyl_plan_s* cyl_plan_t;
 typedef struct cyl_heat_s* cyl_heat_t;
+typedef struct cyl_heat_grad_s* cyl_heat_grad_t;
 
 enum {
     CYL_OK = 0,
@@ -73,9 +74,9 @@ typedef struct {
  * number of launches recorded for each.  Filled by cyl_plan_get_profile. */
 typedef struct {
     double ms_transform_fwd, ms_rhs, ms_adi, ms_residual, ms_recombine,
-           ms_transform_inv, ms_heat_rhs, ms_project;
+           ms_transform_inv, ms_heat_rhs, ms_project, ms_adjoint;
     int n_transform_fwd, n_rhs, n_adi, n_residual, n_recombine,
-        n_transform_inv, n_heat_rhs, n_project;
+        n_transform_inv, n_heat_rhs, n_project, n_adjoint;
 } cyl_profile;
 
 /* Create a plan for an n_r x n_z x n_theta grid (Definition "grid").
@@ -91,6 +92,17 @@ int cyl_plan_destroy(cyl_plan_t plan);
 int cyl_transform_fwd(cyl_plan_t plan, const double* values, double* coeffs);
 /* Coefficients -> values on the grid (the inverse of cyl_transform_fwd). */
 int cyl_transform_inv(cyl_plan_t plan, const double* coeffs, double* values);
+
+/* Transposes of the two transforms with respect to the real inner products
+ * sum x_i y_i of the stored arrays (complex arrays as interleaved doubles; the
+ * imaginary parts of the w = 0 and Nyquist slots are not part of the
+ * coefficient space: ignored on input, written as 0).  The chain rule needs
+ * them to move gradients between value and coefficient space:
+ *   cyl_transform_fwd_adjoint: values_bar = F^T coeffs_bar,
+ *   cyl_transform_inv_adjoint: coeffs_bar = (F^-1)^T values_bar,
+ * with F the map of cyl_transform_fwd.  Both use the plan's workspace. */
+int cyl_transform_fwd_adjoint(cyl_plan_t plan, const double* coeffs_bar, double* values_bar);
+int cyl_transform_inv_adjoint(cyl_plan_t plan, const double* values_bar, double* coeffs_bar);
 
 /* Solve nabla^2 u = f in the cylinder (Section 3, eq. HelmholtzMatEqn without
  * time terms), u = bc on the boundary (bc_lift == NULL: homogeneous).
@@ -119,6 +131,34 @@ int cyl_heat_step(cyl_heat_t h, int n_steps);
 /* Write the newest temperature field to T_out in the given space. */
 int cyl_heat_read(cyl_heat_t h, int space, double* T_out);
 int cyl_heat_destroy(cyl_heat_t h);
+
+/* Reverse-mode differentiation of a BDF1 heat run (the chain rule through the
+ * discrete method of Section 3; the paper gives no adjoint).  For a handle
+ * created with bdf_order = 1, no lift, initial field T_0 = history[0] and
+ * forcing g, a run of n_steps steps gives T_N; for a scalar loss L(T_N) with
+ * gradient T_bar = dL/dT_N the backward call returns dL/dT_0, dL/dg and
+ * dL/dalpha.  Each step's transposed Sylvester solve runs ADI with the forward
+ * step's shifts (the transposed pencil has the same spectra).
+ *
+ * cyl_heat_grad_create: n_steps >= 1; checkpoint_every >= 1 (the forward run
+ *   keeps the state every checkpoint_every steps; the backward run recomputes
+ *   each segment from its checkpoint, i.e. about n_steps - checkpoint_every
+ *   extra forward steps).  Allocates ceil(n_steps / checkpoint_every) states in
+ *   E-layout plus checkpoint_every solution fields (8 (n_r-2)(n_z-2) n_theta
+ *   bytes each) and the transposed ADI tables.  CYL_E_UNSUPPORTED for BDF4 or
+ *   a lifted handle.  The heat handle must outlive the gradient handle.
+ * cyl_heat_grad_forward: restart the heat handle from its T_0 and advance it
+ *   n_steps (afterwards cyl_heat_read gives T_N).  Enqueue only.
+ * cyl_heat_grad_backward: T_bar in `space`; T0_bar and g_bar receive the
+ *   gradients in the same space (value space: arrays [n_theta][n_z][n_r];
+ *   coefficient space: the gradient with respect to the stored doubles of the
+ *   coefficient array); alpha_bar: DEVICE pointer to one double.  Requires a
+ *   preceding forward call; may be repeated for other T_bar.  Enqueue only. */
+int cyl_heat_grad_create(cyl_heat_grad_t* a, cyl_heat_t h, int n_steps, int checkpoint_every);
+int cyl_heat_grad_forward(cyl_heat_grad_t a);
+int cyl_heat_grad_backward(cyl_heat_grad_t a, int space, const double* T_bar, double* T0_bar,
+                           double* g_bar, double* alpha_bar);
+int cyl_heat_grad_destroy(cyl_heat_grad_t a);
 
 /* Host-only (needs no GPU): the ADI parameters the plan would use for
  * wavenumber w of an n_r x n_z grid.  kappa_alpha = 0 selects the Poisson

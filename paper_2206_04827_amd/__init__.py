@@ -27,7 +27,9 @@ STATUS = {0: "CYL_OK", 1: "CYL_E_INVALID_ARG", 2: "CYL_E_UNSUPPORTED", 3: "CYL_E
 EXPORTS = ["cyl_plan_create", "cyl_plan_destroy", "cyl_transform_fwd", "cyl_transform_inv",
            "cyl_poisson_solve", "cyl_heat_create", "cyl_heat_step", "cyl_heat_read",
            "cyl_heat_destroy", "cyl_adi_parameters", "cyl_plan_set_profiling",
-           "cyl_plan_get_profile", "cyl_status_string", "cyl_last_error"]
+           "cyl_plan_get_profile", "cyl_status_string", "cyl_last_error",
+           "cyl_transform_fwd_adjoint", "cyl_transform_inv_adjoint", "cyl_heat_grad_create",
+           "cyl_heat_grad_forward", "cyl_heat_grad_backward", "cyl_heat_grad_destroy"]
 
 
 class CylError(RuntimeError):
@@ -43,7 +45,7 @@ class SolveInfo(ctypes.Structure):
 
 
 _PHASES = ["transform_fwd", "rhs", "adi", "residual", "recombine", "transform_inv", "heat_rhs",
-           "project"]
+           "project", "adjoint"]
 
 
 class Profile(ctypes.Structure):
@@ -80,6 +82,12 @@ def load():
                                ctypes.POINTER(D), ctypes.POINTER(D), I],
         "cyl_plan_set_profiling": [P, I],
         "cyl_plan_get_profile": [P, ctypes.POINTER(Profile)],
+        "cyl_transform_fwd_adjoint": [P, P, P],
+        "cyl_transform_inv_adjoint": [P, P, P],
+        "cyl_heat_grad_create": [ctypes.POINTER(P), P, I, I],
+        "cyl_heat_grad_forward": [P],
+        "cyl_heat_grad_backward": [P, I, P, P, P, P],
+        "cyl_heat_grad_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -183,6 +191,20 @@ class Plan:
         _check(self._lib.cyl_transform_inv(self._h, _ptr(coeffs), _ptr(out)))
         return out
 
+    def transform_fwd_adjoint(self, coeffs_bar, out=None):
+        """values_bar = F^T coeffs_bar (transpose of ``transform_fwd``)."""
+        self._check_tensor(coeffs_bar, CYL_SPACE_COEFF, "coeffs_bar")
+        out = self._out(CYL_SPACE_VALUE, out)
+        _check(self._lib.cyl_transform_fwd_adjoint(self._h, _ptr(coeffs_bar), _ptr(out)))
+        return out
+
+    def transform_inv_adjoint(self, values_bar, out=None):
+        """coeffs_bar = (F^-1)^T values_bar (transpose of ``transform_inv``)."""
+        self._check_tensor(values_bar, CYL_SPACE_VALUE, "values_bar")
+        out = self._out(CYL_SPACE_COEFF, out)
+        _check(self._lib.cyl_transform_inv_adjoint(self._h, _ptr(values_bar), _ptr(out)))
+        return out
+
     def poisson_solve(self, f, bc_lift=None, adi_tol=1e-12, space=None, out=None, info=False):
         """Solve nabla^2 u = f (u = lift on the boundary). Returns u (and info if asked)."""
         if space is None:
@@ -238,6 +260,49 @@ class Heat:
     def close(self):
         if self._h:
             _check(self._lib.cyl_heat_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HeatGrad:
+    """Reverse-mode differentiation of a BDF1 ``Heat`` run of n_steps steps.
+
+    ``forward()`` restarts the heat handle from its initial field and runs it,
+    keeping a checkpoint every ``checkpoint_every`` steps; ``backward(T_bar)``
+    returns (dL/dT0, dL/dg, dL/dalpha) for T_bar = dL/dT_N.
+    """
+
+    def __init__(self, heat, n_steps, checkpoint_every=20):
+        self.heat = heat
+        self.plan = heat.plan
+        self._lib = heat._lib
+        self.n_steps = int(n_steps)
+        self._h = ctypes.c_void_p()
+        _check(self._lib.cyl_heat_grad_create(ctypes.byref(self._h), heat._h, self.n_steps,
+                                              int(checkpoint_every)))
+
+    def forward(self):
+        _check(self._lib.cyl_heat_grad_forward(self._h))
+
+    def backward(self, T_bar, space=None):
+        if space is None:
+            space = CYL_SPACE_COEFF if T_bar.dtype == torch.complex128 else CYL_SPACE_VALUE
+        self.plan._check_tensor(T_bar, space, "T_bar")
+        T0_bar = self.plan._out(space, None)
+        g_bar = self.plan._out(space, None)
+        alpha_bar = torch.empty((), dtype=torch.float64, device=T_bar.device)
+        _check(self._lib.cyl_heat_grad_backward(self._h, space, _ptr(T_bar), _ptr(T0_bar),
+                                                _ptr(g_bar), _ptr(alpha_bar)))
+        return T0_bar, g_bar, alpha_bar
+
+    def close(self):
+        if self._h:
+            _check(self._lib.cyl_heat_grad_destroy(self._h))
             self._h = ctypes.c_void_p()
 
     def __del__(self):

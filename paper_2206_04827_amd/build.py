@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcylspec.so")
 
-SOURCES = ["plan.cpp", "capi.cpp", "transforms.hip", "adi.hip"]
+SOURCES = ["plan.cpp", "capi.cpp", "transforms.hip", "adi.hip", "adjoint.hip"]
 
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
@@ -37,7 +37,7 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=4) as ex:
+    with ThreadPoolExecutor(max_workers=5) as ex:
         results = list(ex.map(_compile, SOURCES))
     objs = []
     for src, obj, rc, log, cmd in results:

@@ -101,14 +101,17 @@ struct DftOwned {
 };
 
 // ADI tables, block descriptors and operator-apply records of one pencil.
+// flip: the transposed pencil in flipped block orientation (the adjoint).
 struct Setup {
     AdiSetup h;
     int passes = 1;
-    DevMem rtab, ztab, vmu, blocks, atab;
+    bool flip = false;
+    DevMem rtab, ztab, vmu, blocks, atab, ztabA_own;
+    const double* ztabA = nullptr;   // B/D column records of this orientation
     std::vector<BlockDesc> hblocks;
 };
 
-enum Phase { PH_FWD, PH_RHS, PH_ADI, PH_RES, PH_REC, PH_INV, PH_HRHS, PH_PROJ, PH_COUNT };
+enum Phase { PH_FWD, PH_RHS, PH_ADI, PH_RES, PH_REC, PH_INV, PH_HRHS, PH_PROJ, PH_ADJ, PH_COUNT };
 
 }  // namespace
 }  // namespace cyl
@@ -139,13 +142,27 @@ struct cyl_plan_s {
 struct cyl_heat_s {
     cyl_plan_t plan = nullptr;
     std::unique_ptr<Setup> setup;
-    double alpha = 0, dt = 0, kappa = 0;
+    double alpha = 0, dt = 0, kappa = 0, tol = 0;
     int order = 1;
     double beta[4] = {0, 0, 0, 0};
     DevMem P[4], Econst, Xt, lift, T0;
     bool has_lift = false;
     int head = 0;          // index of the newest history level
     long long steps = 0;
+};
+
+// Reverse-mode state of a BDF1 heat run: checkpoints of the projected state
+// P_s = C~ X_s B~ every `every` steps (P_0 from T_0), the solutions X_k of the
+// segment being differentiated, and the adjoint work buffers.
+struct cyl_heat_grad_s {
+    cyl_heat_t heat = nullptr;
+    int steps = 0, every = 0, nseg = 0;
+    int seg_holds = -1;                 // segment whose solutions X_k are in seg
+    bool ready = false;                 // a forward run has filled the checkpoints
+    std::unique_ptr<Setup> adj;         // transposed heat pencil, flipped orientation
+    DevMem atab_pois, proj_flip;        // Poisson apply rows; flipped projection rows
+    DevMem ckpt, seg, Pw, Xh, Et, Gsum, partials, planes, vals;
+    int64_t ck_stride = 0, n_partials = 0;
 };
 
 namespace cyl {
@@ -187,11 +204,74 @@ void pass_policy(int m, int n, double eps, int* passes, double* eps_pass) {
     *eps_pass = ps == 2 ? std::sqrt(eps) : eps;
 }
 
-std::unique_ptr<Setup> make_setup(cyl_plan_t pl, double ka, double eps) {
+// Operator-apply records of a pencil (residuals): per w, per r parity, rows of
+// 12 (A row i at i-2..i+3, then C row i at i-2..i+3).  ka == 0: Poisson pencil
+// (A_w, C~); otherwise the heat pencil (C~ - ka A_w, -ka C~).
+std::vector<double> apply_rows(const cyl_plan_s* pl, double ka, bool flip) {
+    const Geometry& g = pl->geo;
+    const int me0 = g.me[0], me1 = g.me[1];
+    std::vector<double> at(static_cast<size_t>(g.nw) * (me0 + me1) * 12, 0.0);
+    for (int w = 0; w < g.nw; ++w) {
+        const Band Aw = band_axpby(1.0, pl->rops.A0, -static_cast<double>(w) * w, pl->rops.Cc);
+        const Band A = ka > 0.0 ? band_axpby(1.0, pl->rops.R2Q, -ka, Aw) : Aw;
+        const Band C = ka > 0.0 ? band_axpby(-ka, pl->rops.R2Q, 0.0, pl->rops.R2Q) : pl->rops.R2Q;
+        size_t base = static_cast<size_t>(w) * (me0 + me1) * 12;
+        for (int pr = 0; pr < 2; ++pr) {
+            Band Ap = band_parity(A, pr), Cp = band_parity(C, pr);
+            if (flip) { Ap = band_flip_transpose(Ap); Cp = band_flip_transpose(Cp); }
+            for (int i = 0; i < Ap.rows; ++i) {
+                for (int t = 0; t < 6; ++t) {
+                    at[base + i * 12 + t] = Ap.get(i, i - 2 + t);
+                    at[base + i * 12 + 6 + t] = Cp.get(i, i - 2 + t);
+                }
+            }
+            base += static_cast<size_t>(Ap.rows) * 12;
+        }
+    }
+    return at;
+}
+
+// z apply records: per z parity, columns of 8 (B column k at rows k-1..k+2,
+// then D column k likewise), B = C02Q^T and D = D2Q^T.
+std::vector<double> z_columns(const cyl_plan_s* pl, bool flip) {
+    const Geometry& g = pl->geo;
+    const Band Bt = band_transpose(pl->zops.C02Q), Dt = band_transpose(pl->zops.D2Q);
+    std::vector<double> za(static_cast<size_t>(g.ne[0] + g.ne[1]) * 8, 0.0);
+    size_t base = 0;
+    for (int pz = 0; pz < 2; ++pz) {
+        Band Bp = band_parity(Bt, pz), Dp = band_parity(Dt, pz);
+        if (flip) { Bp = band_flip_transpose(Bp); Dp = band_flip_transpose(Dp); }
+        for (int k = 0; k < Bp.cols; ++k)
+            for (int t = 0; t < 4; ++t) {
+                za[base + k * 8 + t] = Bp.get(k - 1 + t, k);
+                za[base + k * 8 + 4 + t] = Dp.get(k - 1 + t, k);
+            }
+        base += static_cast<size_t>(Bp.cols) * 8;
+    }
+    return za;
+}
+
+// Projection records (heat history C~ X B~): A = R2Q rows, C = 0, shared by all w.
+std::vector<double> projection_rows(const cyl_plan_s* pl, bool flip) {
+    const Geometry& g = pl->geo;
+    std::vector<double> ap(static_cast<size_t>(g.me[0] + g.me[1]) * 12, 0.0);
+    size_t base = 0;
+    for (int pr = 0; pr < 2; ++pr) {
+        Band Cp = band_parity(pl->rops.R2Q, pr);
+        if (flip) Cp = band_flip_transpose(Cp);
+        for (int i = 0; i < Cp.rows; ++i)
+            for (int t = 0; t < 6; ++t) ap[base + i * 12 + t] = Cp.get(i, i - 2 + t);
+        base += static_cast<size_t>(Cp.rows) * 12;
+    }
+    return ap;
+}
+
+std::unique_ptr<Setup> make_setup(cyl_plan_t pl, double ka, double eps, bool flip = false) {
     auto s = std::make_unique<Setup>();
     double eps_pass;
     pass_policy(pl->m, pl->n, eps, &s->passes, &eps_pass);
-    s->h = build_adi_setup(pl->geo, pl->rops, pl->zops, ka, eps_pass);
+    s->h = build_adi_setup(pl->geo, pl->rops, pl->zops, ka, eps_pass, flip);
+    s->flip = flip;
     const Geometry& g = pl->geo;
     const int me0 = g.me[0], me1 = g.me[1], ne0 = g.ne[0], ne1 = g.ne[1];
     // block offsets inside a plane: (pr, pz) = (0,0), (0,1), (1,0), (1,1)
@@ -225,26 +305,13 @@ std::unique_ptr<Setup> make_setup(cyl_plan_t pl, double ka, double eps) {
     upload(s->ztab, s->h.ztab);
     upload(s->vmu, s->h.vmu);
     upload(s->blocks, s->hblocks);
-    // operator-apply records of the pencil (residuals): per w, per r parity,
-    // A row then C row at offsets -2..3
-    std::vector<double> at(static_cast<size_t>(g.nw) * (me0 + me1) * 12, 0.0);
-    for (int w = 0; w < g.nw; ++w) {
-        const Band Aw = band_axpby(1.0, pl->rops.A0, -static_cast<double>(w) * w, pl->rops.Cc);
-        const Band A = ka > 0.0 ? band_axpby(1.0, pl->rops.R2Q, -ka, Aw) : Aw;
-        const Band C = ka > 0.0 ? band_axpby(-ka, pl->rops.R2Q, 0.0, pl->rops.R2Q) : pl->rops.R2Q;
-        size_t base = static_cast<size_t>(w) * (me0 + me1) * 12;
-        for (int pr = 0; pr < 2; ++pr) {
-            const Band Ap = band_parity(A, pr), Cp = band_parity(C, pr);
-            for (int i = 0; i < Ap.rows; ++i) {
-                for (int t = 0; t < 6; ++t) {
-                    at[base + i * 12 + t] = Ap.get(i, i - 2 + t);
-                    at[base + i * 12 + 6 + t] = Cp.get(i, i - 2 + t);
-                }
-            }
-            base += static_cast<size_t>(Ap.rows) * 12;
-        }
+    upload(s->atab, apply_rows(pl, ka, flip));
+    if (flip) {
+        upload(s->ztabA_own, z_columns(pl, true));
+        s->ztabA = s->ztabA_own.as<double>();
+    } else {
+        s->ztabA = pl->ztabA.as<double>();
     }
-    upload(s->atab, at);
     return s;
 }
 
@@ -303,6 +370,31 @@ void transform_inv(cyl_plan_t pl, const double2* coeffs, double* values) {
     hip_check(launch_theta_inv(W, values, g.m, g.n, g.p, pl->dth.view, pl->stream), "theta_inv");
 }
 
+// values = F^T coeffs (the transpose of transform_fwd with respect to the real
+// inner products of both arrays).  U is overwritten; it must not be planesA.
+void transform_fwd_adjoint(cyl_plan_t pl, double2* U, double* values) {
+    const Geometry& g = pl->geo;
+    {
+        Scope sc(pl, PH_ADJ);
+        hip_check(launch_scale_planes(U, g.m, g.n, g.p, 0, pl->stream), "scale planes");
+    }
+    transform_inv(pl, U, values);
+    Scope sc(pl, PH_ADJ);
+    hip_check(launch_scale_values(values, values, g.m, g.n, g.p, 0, pl->stream), "scale values");
+}
+
+// coeffs = F^-T values (the transpose of transform_inv); tmp holds p n m doubles.
+void transform_inv_adjoint(cyl_plan_t pl, const double* values, double* tmp, double2* coeffs) {
+    const Geometry& g = pl->geo;
+    {
+        Scope sc(pl, PH_ADJ);
+        hip_check(launch_scale_values(values, tmp, g.m, g.n, g.p, 1, pl->stream), "scale values");
+    }
+    transform_fwd(pl, tmp, coeffs);
+    Scope sc(pl, PH_ADJ);
+    hip_check(launch_scale_planes(coeffs, g.m, g.n, g.p, 1, pl->stream), "scale planes");
+}
+
 // ADI solve of all blocks: X <- solution of A X B + C X D = E (setup pencil).
 void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X) {
     const Geometry& g = pl->geo;
@@ -314,7 +406,7 @@ void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X) {
             hip_check(launch_apply2(s->blocks.as<BlockDesc>(), nblk, g.me[0], g.ne[0], E, 1.0, X, 1.0, 1.0,
                                     pl->R.as<double>(), s->atab.as<double>(),
                                     static_cast<int64_t>(g.me[0] + g.me[1]) * 12,
-                                    pl->ztabA.as<double>(), pl->stream), "residual");
+                                    s->ztabA, pl->stream), "residual");
             rhs = pl->R.as<double>();
         }
         Scope sc(pl, PH_ADI);
@@ -335,7 +427,7 @@ void check_residual(cyl_plan_t pl, Setup* s, const double* E, const double* X, d
         hip_check(launch_apply2(s->blocks.as<BlockDesc>(), nblk, g.me[0], g.ne[0], E, 1.0, X, 1.0, 1.0,
                                 pl->R.as<double>(), s->atab.as<double>(),
                                 static_cast<int64_t>(g.me[0] + g.me[1]) * 12,
-                                pl->ztabA.as<double>(), pl->stream), "residual");
+                                s->ztabA, pl->stream), "residual");
     }
     hip_check(hipMemsetAsync(pl->acc.p, 0, 3 * sizeof(double), pl->stream), "memset");
     hip_check(launch_norms(pl->R.as<double>(), E, g.etotal_elems, X, g.total_elems, pl->acc.as<double>(),
@@ -408,30 +500,8 @@ void build_plan(cyl_plan_t pl) {
     std::vector<int> pof(2 * g.nw, -1);
     for (int i = 0; i < g.nplanes; ++i) pof[2 * g.plane_w[i] + g.plane_part[i]] = i;
     upload(pl->plane_of, pof);
-    // z apply records: B column k at rows k-1..k+2, D column likewise
-    const Band Bt = band_transpose(pl->zops.C02Q), Dt = band_transpose(pl->zops.D2Q);
-    std::vector<double> za(static_cast<size_t>(g.ne[0] + g.ne[1]) * 8, 0.0);
-    size_t base = 0;
-    for (int pz = 0; pz < 2; ++pz) {
-        const Band Bp = band_parity(Bt, pz), Dp = band_parity(Dt, pz);
-        for (int k = 0; k < Bp.cols; ++k)
-            for (int t = 0; t < 4; ++t) {
-                za[base + k * 8 + t] = Bp.get(k - 1 + t, k);
-                za[base + k * 8 + 4 + t] = Dp.get(k - 1 + t, k);
-            }
-        base += static_cast<size_t>(Bp.cols) * 8;
-    }
-    upload(pl->ztabA, za);
-    // projection records (heat history): A = R2 Q rows, C = 0, shared by all w
-    std::vector<double> ap(static_cast<size_t>(g.me[0] + g.me[1]) * 12, 0.0);
-    base = 0;
-    for (int pr = 0; pr < 2; ++pr) {
-        const Band Cp = band_parity(pl->rops.R2Q, pr);
-        for (int i = 0; i < Cp.rows; ++i)
-            for (int t = 0; t < 6; ++t) ap[base + i * 12 + t] = Cp.get(i, i - 2 + t);
-        base += static_cast<size_t>(Cp.rows) * 12;
-    }
-    upload(pl->atab_proj, ap);
+    upload(pl->ztabA, z_columns(pl, false));
+    upload(pl->atab_proj, projection_rows(pl, false));
     // workspace
     const size_t planes_bytes = static_cast<size_t>(g.nw) * n * m * sizeof(double2);
     const size_t blk_bytes = static_cast<size_t>(g.total_elems) * sizeof(double);
@@ -472,6 +542,28 @@ void build_plan(cyl_plan_t pl) {
                      m, n, p, g.me[0], g.me[1], g.ne[0], g.ne[1], pl->use_lds ? "LDS-resident" : "HBM-resident",
                      pl->adi_threads, pl->lds_bytes, max_lds, pl->dr.t.Nb, pl->dz.t.Nb, pl->dth.t.Nb);
 }
+
+// One BDF1 step of the handle's pencil: X = S^-1 (Pin + Econst), Pout = C~ X B~.
+void heat_step_bdf1(cyl_heat_t h, const double* Pin, double* X, double* Pout) {
+    cyl_plan_s* pl = h->plan;
+    const Geometry& g = pl->geo;
+    Setup* s = h->setup.get();
+    const double* P[1] = {Pin};
+    const double one = 1.0;
+    {
+        Scope sc(pl, PH_HRHS);
+        hip_check(launch_heat_rhs(pl->E.as<double>(), P, &one, 1, h->Econst.as<double>(), g.etotal_elems,
+                                  pl->stream), "heat rhs");
+    }
+    adi_solve(pl, s, pl->E.as<double>(), X);
+    Scope sc(pl, PH_PROJ);
+    hip_check(launch_apply2(s->blocks.as<BlockDesc>(), static_cast<int>(s->hblocks.size()), g.me[0], g.ne[0],
+                            nullptr, 0.0, X, -1.0, 0.0, Pout, pl->atab_proj.as<double>(), 0,
+                            pl->ztabA.as<double>(), pl->stream), "project");
+}
+
+double* ckpt_slot(cyl_heat_grad_s* a, int j) { return a->ckpt.as<double>() + j * a->ck_stride; }
+double* seg_slot(cyl_heat_grad_s* a, int t) { return a->seg.as<double>() + t * a->heat->plan->geo.total_elems; }
 
 }  // namespace
 }  // namespace cyl
@@ -589,7 +681,7 @@ int cyl_heat_create(cyl_heat_t* h, cyl_plan_t plan, double alpha, double dt, int
         const Geometry& geo = pl->geo;
         auto H = std::make_unique<cyl_heat_s>();
         H->plan = pl;
-        H->alpha = alpha; H->dt = dt; H->order = bdf_order;
+        H->alpha = alpha; H->dt = dt; H->order = bdf_order; H->tol = adi_tol;
         if (bdf_order == 1) { H->kappa = dt; H->beta[0] = 1.0; }
         else {
             H->kappa = 12.0 * dt / 25.0;
@@ -758,6 +850,179 @@ int cyl_plan_get_profile(cyl_plan_t plan, cyl_profile* out) {
         out->ms_transform_inv = ms[PH_INV]; out->n_transform_inv = cnt[PH_INV];
         out->ms_heat_rhs = ms[PH_HRHS]; out->n_heat_rhs = cnt[PH_HRHS];
         out->ms_project = ms[PH_PROJ]; out->n_project = cnt[PH_PROJ];
+        out->ms_adjoint = ms[PH_ADJ]; out->n_adjoint = cnt[PH_ADJ];
+    });
+}
+
+int cyl_transform_fwd_adjoint(cyl_plan_t plan, const double* coeffs_bar, double* values_bar) {
+    return guarded([&] {
+        if (!plan || !coeffs_bar || !values_bar) fail(CYL_E_INVALID_ARG, "NULL argument");
+        const Geometry& g = plan->geo;
+        const size_t bytes = static_cast<size_t>(g.nw) * g.n * g.m * sizeof(double2);
+        hip_check(hipMemcpyAsync(plan->planesB.p, coeffs_bar, bytes, hipMemcpyDeviceToDevice, plan->stream), "copy");
+        transform_fwd_adjoint(plan, plan->planesB.as<double2>(), values_bar);
+    });
+}
+
+int cyl_transform_inv_adjoint(cyl_plan_t plan, const double* values_bar, double* coeffs_bar) {
+    return guarded([&] {
+        if (!plan || !coeffs_bar || !values_bar) fail(CYL_E_INVALID_ARG, "NULL argument");
+        // planesA holds (p/2 + 1) n m complex >= p n m doubles: room for the scaled values
+        transform_inv_adjoint(plan, values_bar, plan->planesA.as<double>(), reinterpret_cast<double2*>(coeffs_bar));
+    });
+}
+
+int cyl_heat_grad_create(cyl_heat_grad_t* out, cyl_heat_t h, int n_steps, int checkpoint_every) {
+    return guarded([&] {
+        if (!out) fail(CYL_E_INVALID_ARG, "handle pointer is NULL");
+        *out = nullptr;
+        if (!h) fail(CYL_E_INVALID_ARG, "heat handle is NULL");
+        if (n_steps < 1) fail(CYL_E_INVALID_ARG, "n_steps must be >= 1");
+        if (checkpoint_every < 1) fail(CYL_E_INVALID_ARG, "checkpoint_every must be >= 1");
+        if (h->order != 1) fail(CYL_E_UNSUPPORTED, "differentiation supports BDF1 only");
+        if (h->has_lift) fail(CYL_E_UNSUPPORTED, "differentiation supports homogeneous Dirichlet data only");
+        cyl_plan_s* pl = h->plan;
+        const Geometry& g = pl->geo;
+        auto a = std::make_unique<cyl_heat_grad_s>();
+        a->heat = h;
+        a->steps = n_steps;
+        a->every = std::min(checkpoint_every, n_steps);
+        a->nseg = (n_steps + a->every - 1) / a->every;
+        a->adj = make_setup(pl, h->kappa * h->alpha, h->tol, true);
+        upload(a->atab_pois, apply_rows(pl, 0.0, false));
+        upload(a->proj_flip, projection_rows(pl, true));
+        // checkpoints: E-layout slots, zero padding rows
+        a->ck_stride = g.etotal_elems + 64;
+        const size_t ck_bytes = static_cast<size_t>(a->nseg) * a->ck_stride * sizeof(double);
+        a->ckpt.alloc(ck_bytes);
+        hip_check(hipMemset(a->ckpt.p, 0, ck_bytes), "hipMemset");
+        a->seg.alloc(static_cast<size_t>(a->every) * g.total_elems * sizeof(double));
+        alloc_elayout(a->Pw, g);
+        alloc_elayout(a->Xh, g);
+        a->Et.alloc(static_cast<size_t>(g.total_elems) * sizeof(double));
+        a->Gsum.alloc(static_cast<size_t>(g.total_elems) * sizeof(double));
+        a->n_partials = apply_dot_partials(static_cast<int>(a->adj->hblocks.size()), g.me[0], g.ne[0]);
+        a->partials.alloc(static_cast<size_t>(a->n_partials) * sizeof(double));
+        a->planes.alloc(static_cast<size_t>(g.nw) * g.n * g.m * sizeof(double2));
+        a->vals.alloc(static_cast<size_t>(g.p) * g.n * g.m * sizeof(double));
+        *out = a.release();
+    });
+}
+
+int cyl_heat_grad_forward(cyl_heat_grad_t a) {
+    return guarded([&] {
+        if (!a) fail(CYL_E_INVALID_ARG, "handle is NULL");
+        cyl_heat_t h = a->heat;
+        cyl_plan_s* pl = h->plan;
+        const Geometry& g = pl->geo;
+        const int N = a->steps, K = a->every, s_last = (a->nseg - 1) * K;
+        // P_0 = [R2 T_0 C02^T]_tau from the handle's initial temperature
+        {
+            Scope sc(pl, PH_RHS);
+            hip_check(launch_rhs3(h->T0.as<double2>(), nullptr, 1.0, 0.0, 0.0, ckpt_slot(a, 0),
+                                  h->setup->blocks.as<BlockDesc>(), g.nplanes, g.m, g.n, pl->rhs,
+                                  pl->stream), "initial projection");
+        }
+        const double* cur = ckpt_slot(a, 0);
+        for (int k = 1; k <= N; ++k) {
+            double* X = k > s_last ? seg_slot(a, k - s_last - 1) : h->Xt.as<double>();
+            double* Pout = (k % K == 0 && k < N) ? ckpt_slot(a, k / K) : a->Pw.as<double>();
+            heat_step_bdf1(h, cur, X, Pout);
+            cur = Pout;
+        }
+        // leave the heat handle at step N
+        const size_t eb = static_cast<size_t>(g.etotal_elems) * sizeof(double);
+        hip_check(hipMemcpyAsync(h->P[0].p, cur, eb, hipMemcpyDeviceToDevice, pl->stream), "copy state");
+        hip_check(hipMemcpyAsync(h->Xt.p, seg_slot(a, N - s_last - 1),
+                                 static_cast<size_t>(g.total_elems) * sizeof(double), hipMemcpyDeviceToDevice,
+                                 pl->stream), "copy state");
+        h->head = 0;
+        h->steps = N;
+        a->seg_holds = a->nseg - 1;
+        a->ready = true;
+    });
+}
+
+int cyl_heat_grad_backward(cyl_heat_grad_t a, int space, const double* T_bar, double* T0_bar,
+                           double* g_bar, double* alpha_bar) {
+    return guarded([&] {
+        if (!a || !T_bar || !T0_bar || !g_bar || !alpha_bar) fail(CYL_E_INVALID_ARG, "NULL argument");
+        validate_space(space);
+        if (!a->ready) fail(CYL_E_INVALID_ARG, "cyl_heat_grad_forward has not been run");
+        cyl_heat_t h = a->heat;
+        cyl_plan_s* pl = h->plan;
+        const Geometry& g = pl->geo;
+        Setup* adj = a->adj.get();
+        const BlockDesc* fblocks = h->setup->blocks.as<BlockDesc>();
+        const BlockDesc* ablocks = adj->blocks.as<BlockDesc>();
+        const int nblk = static_cast<int>(adj->hblocks.size());
+        const int N = a->steps, K = a->every;
+        const double kappa = h->kappa;
+        const int64_t xb = g.total_elems;
+        hip_check(hipMemsetAsync(a->Gsum.p, 0, static_cast<size_t>(xb) * sizeof(double), pl->stream), "memset");
+        hip_check(hipMemsetAsync(a->partials.p, 0, static_cast<size_t>(a->n_partials) * sizeof(double), pl->stream),
+                  "memset");
+        // seed: Xbar_N = Q^T Ubar_N Q, Ubar_N = F^-T T_bar
+        const double2* Ubar = reinterpret_cast<const double2*>(T_bar);
+        if (space == CYL_SPACE_VALUE) {
+            transform_inv_adjoint(pl, T_bar, a->vals.as<double>(), a->planes.as<double2>());
+            Ubar = a->planes.as<double2>();
+        }
+        {
+            Scope sc(pl, PH_ADJ);
+            hip_check(launch_recombine_t(Ubar, 1.0, a->Xh.as<double>(), ablocks, nblk,
+                                         static_cast<int64_t>(g.me[0]) * g.ne[0], g.m, g.n, pl->stream),
+                      "recombine_t");
+        }
+        const int64_t awstride = static_cast<int64_t>(g.me[0] + g.me[1]) * 12;
+        for (int j = a->nseg - 1; j >= 0; --j) {
+            const int s0 = j * K, len = std::min(K, N - s0);
+            if (a->seg_holds != j) {                     // recompute X_{s0+1..s0+len}
+                const double* cur = ckpt_slot(a, j);
+                for (int t = 1; t <= len; ++t) {
+                    heat_step_bdf1(h, cur, seg_slot(a, t - 1), a->Pw.as<double>());
+                    cur = a->Pw.as<double>();
+                }
+                a->seg_holds = j;
+            }
+            for (int t = len; t >= 1; --t) {
+                const int k = s0 + t;
+                // Ebar_k = S^-T Xbar_k (flipped: the ordinary ADI on the flipped pencil)
+                adi_solve(pl, adj, a->Xh.as<double>(), a->Et.as<double>());
+                Scope sc(pl, PH_ADJ);
+                hip_check(launch_apply_dot(fblocks, nblk, g.me[0], g.ne[0], seg_slot(a, t - 1), a->Et.as<double>(),
+                                           a->atab_pois.as<double>(), awstride, pl->ztabA.as<double>(),
+                                           a->partials.as<double>(), pl->stream), "alpha term");
+                hip_check(launch_axpy(a->Gsum.as<double>(), a->Et.as<double>(), 1.0, xb, pl->stream), "accumulate");
+                if (k > 1)                                // Xbar_{k-1} = C~^T Ebar_k B~^T
+                    hip_check(launch_apply2(ablocks, nblk, g.me[0], g.ne[0], nullptr, 0.0, a->Et.as<double>(), -1.0,
+                                            0.0, a->Xh.as<double>(), a->proj_flip.as<double>(), 0, adj->ztabA,
+                                            pl->stream), "project_t");
+            }
+        }
+        // T0_bar = F^T [R2^T Ebar_1 C02], g_bar = F^T kappa [R2^T (sum_k Ebar_k) C02]
+        const double* srcs[2] = {a->Et.as<double>(), a->Gsum.as<double>()};
+        const double scales[2] = {1.0, kappa};
+        double* outs[2] = {T0_bar, g_bar};
+        for (int q = 0; q < 2; ++q) {
+            double2* U = space == CYL_SPACE_COEFF ? reinterpret_cast<double2*>(outs[q]) : a->planes.as<double2>();
+            {
+                Scope sc(pl, PH_ADJ);
+                hip_check(launch_rhs_t(srcs[q], scales[q], U, pl->plane_of.as<int>(), ablocks, g.nw, g.m, g.n,
+                                       pl->rhs, pl->stream), "rhs_t");
+            }
+            if (space == CYL_SPACE_VALUE) transform_fwd_adjoint(pl, U, outs[q]);
+        }
+        Scope sc(pl, PH_ADJ);
+        hip_check(launch_sum(a->partials.as<double>(), a->n_partials, kappa, alpha_bar, pl->stream), "alpha sum");
+    });
+}
+
+int cyl_heat_grad_destroy(cyl_heat_grad_t a) {
+    return guarded([&] {
+        if (!a) fail(CYL_E_INVALID_ARG, "handle is NULL");
+        (void)hipStreamSynchronize(a->heat->plan->stream);
+        delete a;
     });
 }
 

@@ -97,4 +97,31 @@ hipError_t launch_heat_rhs(double* E, const double* const* P, const double* beta
 hipError_t launch_norms(const double* R, const double* E, int64_t etotal, const double* X,
                         int64_t xtotal, double* acc, hipStream_t s);
 
+// ---- adjoint (transposed) operators, flipped block orientation ----
+// Adjoint quantities of a parity block are stored flipped: block element
+// (i', k') holds the entry (me-1-i', ne-1-k') (see adjoint.hip).
+// out (E-layout, flipped) = s * Q_m^T U Q_n per block (transposed recombination).
+hipError_t launch_recombine_t(const double2* U, double s, double* out, const BlockDesc* blocks,
+                              int nblocks, int64_t max_block_elems, int m, int n, hipStream_t st);
+// U (planes) = s * R2^T Y C02 restricted to tau rows (transposed tau right side);
+// Y flipped in X-layout.
+hipError_t launch_rhs_t(const double* Yf, double s, double2* U, const int* plane_of,
+                        const BlockDesc* blocks, int nw, int m, int n, const RhsTables& t,
+                        hipStream_t st);
+// y += a x
+hipError_t launch_axpy(double* y, const double* x, double a, int64_t count, hipStream_t st);
+// partials[tile] += sum Yf~ . (A X B + C X D) over each 32 x 32 tile (records as launch_apply2)
+int64_t apply_dot_partials(int nblocks, int me0, int ne0);
+hipError_t launch_apply_dot(const BlockDesc* blocks, int nblocks, int me0, int ne0, const double* X,
+                            const double* Yf, const double* atab, int64_t a_wstride,
+                            const double* ztabA, double* partials, hipStream_t st);
+// out[0] = scale * sum(partials) (one workgroup, deterministic order)
+hipError_t launch_sum(const double* partials, int64_t count, double scale, double* out,
+                      hipStream_t st);
+// Diagonal factors of the transposed transforms: mode 0 before the inverse
+// transform (F^T), mode 1 after the forward transform (F^-T); see adjoint.hip.
+hipError_t launch_scale_planes(double2* U, int m, int n, int p, int mode, hipStream_t st);
+hipError_t launch_scale_values(const double* in, double* out, int m, int n, int p, int mode,
+                               hipStream_t st);
+
 }  // namespace cyl

@@ -82,6 +82,19 @@ Band band_transpose(const Band& A) {
     return T;
 }
 
+Band band_flip_transpose(const Band& A) {
+    if (A.rows != A.cols) throw std::logic_error("band_flip_transpose: matrix is not square");
+    const int N = A.rows;
+    Band F(N, N, A.lo, A.hi);
+    for (int i = 0; i < N; ++i)
+        for (int d = -A.lo; d <= A.hi; ++d) {
+            const int j = i + d;
+            if (j < 0 || j >= N) continue;
+            F.set(i, j, A.get(N - 1 - j, N - 1 - i));
+        }
+    return F;
+}
+
 Band band_parity(const Band& A, int p) {
     for (int i = 0; i < A.rows; ++i)
         for (int d = -A.lo; d <= A.hi; ++d) {
@@ -456,7 +469,8 @@ void mode_parameters(const DirOps& r, const DirOps& z, int w, double ka, double 
     }
 }
 
-AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, double ka, double eps) {
+AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, double ka, double eps,
+                         bool flip) {
     AdiSetup s;
     s.kappa_alpha = ka; s.eps = eps; s.nw = g.nw;
     double zc, zd;
@@ -464,7 +478,10 @@ AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, do
 
     const Band Bt = band_transpose(z.C02Q), Dt = band_transpose(z.D2Q);
     Band Bp[2], Dp[2];
-    for (int par = 0; par < 2; ++par) { Bp[par] = band_parity(Bt, par); Dp[par] = band_parity(Dt, par); }
+    for (int par = 0; par < 2; ++par) {
+        Bp[par] = band_parity(Bt, par); Dp[par] = band_parity(Dt, par);
+        if (flip) { Bp[par] = band_flip_transpose(Bp[par]); Dp[par] = band_flip_transpose(Dp[par]); }
+    }
     // records per shift: both parity blocks, rows padded to a multiple of 8
     const int me_sum = g.mp[0] + g.mp[1], ne_sum = g.np[0] + g.np[1];
 
@@ -488,7 +505,10 @@ AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, do
         const Band A = ka > 0.0 ? band_axpby(1.0, r.R2Q, -ka, Aw) : Aw;
         const Band C = ka > 0.0 ? band_axpby(-ka, r.R2Q, 0.0, r.R2Q) : r.R2Q;
         Band Ap[2], Cp[2];
-        for (int par = 0; par < 2; ++par) { Ap[par] = band_parity(A, par); Cp[par] = band_parity(C, par); }
+        for (int par = 0; par < 2; ++par) {
+            Ap[par] = band_parity(A, par); Cp[par] = band_parity(C, par);
+            if (flip) { Ap[par] = band_flip_transpose(Ap[par]); Cp[par] = band_flip_transpose(Cp[par]); }
+        }
         const int J = s.J[w];
         for (int j = 0; j < J; ++j) {
             const double uj = U[w][j], vj = V[w][j];

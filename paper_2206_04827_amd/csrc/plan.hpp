@@ -24,6 +24,9 @@ Band band_mul(const Band& A, const Band& B);
 Band band_axpby(double alpha, const Band& A, double beta, const Band& B);
 Band band_cut(const Band& A, int rows, int cols);
 Band band_transpose(const Band& A);
+// J A^T J for square A (J reverses the index order).  Same band widths as A;
+// it turns a transposed banded solve into one of the original shape.
+Band band_flip_transpose(const Band& A);
 // Rows/columns of one index parity (p = 0 even, 1 odd); the operators here
 // never couple the two parities, which is checked.
 Band band_parity(const Band& A, int p);
@@ -101,9 +104,12 @@ Geometry make_geometry(int m, int n, int p);
 
 // Build the ADI setup for pencil (A_w - kappa_alpha-scaled) and tolerance eps.
 // kappa_alpha == 0: Poisson pencil (A_w, C).  Otherwise the heat pencil
-// (C - ka A_w, -ka C).
+// (C - ka A_w, -ka C).  flip: the transposed equation
+// A^T Y B^T + C^T Y D^T = F written for Y~ = J Y J, F~ = J F J inside every
+// parity block, i.e. the pencil (J A^T J, J C^T J), (J B^T J, J D^T J); its
+// spectra, shifts and iteration counts are those of the untransposed pencil.
 AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z,
-                         double kappa_alpha, double eps);
+                         double kappa_alpha, double eps, bool flip = false);
 
 // Bounds/J/shifts of one wavenumber (shared by the setup and the host query).
 void mode_parameters(const DirOps& r, const DirOps& z, int w, double kappa_alpha,

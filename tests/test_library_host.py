@@ -64,6 +64,15 @@ def test_null_arguments_are_rejected(lib):
     assert lib.cyl_heat_destroy(None) == 1
     assert lib.cyl_plan_set_profiling(None, 1) == 1
     assert lib.cyl_plan_get_profile(None, None) == 1
+    assert lib.cyl_transform_fwd_adjoint(None, None, None) == 1
+    assert lib.cyl_transform_inv_adjoint(None, None, None) == 1
+    g = ctypes.c_void_p()
+    assert lib.cyl_heat_grad_create(ctypes.byref(g), None, 10, 2) == 1
+    assert not g.value
+    assert lib.cyl_heat_grad_create(None, None, 10, 2) == 1
+    assert lib.cyl_heat_grad_forward(None) == 1
+    assert lib.cyl_heat_grad_backward(None, 0, None, None, None, None) == 1
+    assert lib.cyl_heat_grad_destroy(None) == 1
 
 
 def test_adi_parameter_validation():
