@@ -10,7 +10,11 @@ Prints one JSON line.  Besides the headline value it carries:
                 from HIP events recorded around every ADI launch on the
                 plan's stream inside the timed region;
   cpu_baseline  the CPU oracle timed on a bounded sample of the same solve;
-  heat_128      forward BDF1 heat steps per second on the 128^3 grid.
+  heat_128      forward BDF1 heat steps per second on the 128^3 grid;
+  heat_fwd_adjoint_192
+                forward + adjoint BDF1 heat steps per second at 192^3: 200
+                steps, alpha = 1, dt = 1e-3, checkpoint every 20 steps, loss
+                |T_N - T_target|^2, gradients for T0, g and alpha.
 """
 
 import argparse
@@ -46,6 +50,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-heat", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-reps", type=int, default=2)
     ap.add_argument("--cpu-modes", type=int, default=16,
                     help="wavenumbers the CPU oracle solves in its timed sample")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -85,6 +91,67 @@ def cpu_baseline(m, n, p, seed, nmodes):
                        "%d of %d wavenumbers (every %d-th) and scaled to all; %.2f s measured, "
                        "%.1f s extrapolated") % (m, len(ls), p, max(1, p // nmodes),
                                                  t_fwd + t_inv + t_modes, t_total)}
+
+
+def heat_fwd_adjoint(cyl, torch, synth, reps, size=192, steps=200, every=20):
+    """Forward + adjoint of a BDF1 heat run (gradients w.r.t. T0, g, alpha)."""
+    m = n = p = size
+    S = synth.SEED_BASE
+    pl = cyl.Plan(m, n, p)
+    T0 = torch.from_numpy(synth.eigenmode_values(synth.eigenmode_params(S + 5), m, n, p)).cuda()
+    g = pl.transform_inv(torch.from_numpy(synth.smooth_coeffs(m, n, p, S + 6)).cuda())
+    Tt = pl.transform_inv(torch.from_numpy(synth.smooth_coeffs(m, n, p, S + 7)).cuda())
+    H = cyl.Heat(pl, [T0], g, 1.0, 1e-3, 1, 1e-12)
+    G = cyl.HeatGrad(H, steps, every)
+
+    def one():
+        G.forward()
+        TN = H.read()
+        return G.backward(2.0 * (TN - Tt))
+
+    one()                                  # warm-up (first launches)
+    torch.cuda.synchronize()
+    pl.set_profiling(True)
+    pl.profile()
+    t_fwd = t_all = 0.0
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G.forward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        TN = H.read()
+        T0b, gb, ab = G.backward(2.0 * (TN - Tt))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_fwd += t1 - t0
+        t_all += t2 - t0
+    prof = pl.profile()
+    pl.set_profiling(False)
+    # plain forward run of the same problem (no checkpoints) for comparison
+    H2 = cyl.Heat(pl, [T0], g, 1.0, 1e-3, 1, 1e-12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H2.step(steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    nseg = (steps + every - 1) // every
+    res = {"steps_per_s": steps * reps / t_all, "ms_per_fwd_adjoint_run": 1e3 * t_all / reps,
+           "ms_forward_part": 1e3 * t_fwd / reps, "ms_backward_part": 1e3 * (t_all - t_fwd) / reps,
+           "plain_forward_steps_per_s": steps / t_plain,
+           "heat_solves_per_run": {"forward": steps, "recompute": steps - min(every, steps),
+                                   "transposed": steps},
+           "config": {"workload": "heat_bdf1_%d^3_fwd_adjoint" % size, "steps": steps,
+                      "checkpoint_every": every, "checkpoints": nseg, "alpha": 1.0, "dt": 1e-3,
+                      "adi_tol": 1e-12, "loss": "sum (T_N - T_target)^2",
+                      "gradients": ["T0", "g", "alpha"]},
+           "alpha_grad": float(ab),
+           "phase_ms_per_run": {k[3:]: round(prof[k] / reps, 3) for k in prof if k.startswith("ms_")}}
+    G.close()
+    H.close()
+    H2.close()
+    pl.close()
+    return res
 
 
 def main():
@@ -164,9 +231,12 @@ def main():
         torch.cuda.synchronize()
         th = time.perf_counter() - t0
         out["heat_128"] = {"steps_per_s": 100 / th, "ms_per_step": 1e3 * th / 100,
-                           "note": "forward BDF1 steps only (no adjoint in this build)"}
+                           "note": "forward BDF1 steps only"}
         H.close()
         hp.close()
+
+    if not args.no_adjoint:
+        out["heat_fwd_adjoint_192"] = heat_fwd_adjoint(cyl, torch, synth, args.adjoint_reps)
 
     if args.calibrate_copy:
         a = torch.ones(1 << 26, dtype=torch.float64, device="cuda")

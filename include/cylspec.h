@@ -126,7 +126,9 @@ int cyl_poisson_solve(cyl_plan_t plan, int space, const double* f, const double*
 int cyl_heat_create(cyl_heat_t* h, cyl_plan_t plan, double alpha, double dt, int bdf_order,
                     double adi_tol, int space, const double* const* history,
                     const double* g, const double* bc_lift);
-/* Advance n_steps >= 0 steps (enqueue only; allocates nothing). */
+/* Advance n_steps >= 0 steps (enqueue only; allocates nothing).  The plan
+ * must stay alive while the handle is used; cyl_heat_destroy does not touch
+ * the plan, so the two may be destroyed in either order. */
 int cyl_heat_step(cyl_heat_t h, int n_steps);
 /* Write the newest temperature field to T_out in the given space. */
 int cyl_heat_read(cyl_heat_t h, int space, double* T_out);
@@ -146,7 +148,8 @@ int cyl_heat_destroy(cyl_heat_t h);
  *   extra forward steps).  Allocates ceil(n_steps / checkpoint_every) states in
  *   E-layout plus checkpoint_every solution fields (8 (n_r-2)(n_z-2) n_theta
  *   bytes each) and the transposed ADI tables.  CYL_E_UNSUPPORTED for BDF4 or
- *   a lifted handle.  The heat handle must outlive the gradient handle.
+ *   a lifted handle.  Every call but cyl_heat_grad_destroy needs the heat
+ *   handle and its plan alive; the handles may be destroyed in any order.
  * cyl_heat_grad_forward: restart the heat handle from its T_0 and advance it
  *   n_steps (afterwards cyl_heat_read gives T_N).  Enqueue only.
  * cyl_heat_grad_backward: T_bar in `space`; T0_bar and g_bar receive the

@@ -141,6 +141,7 @@ struct cyl_plan_s {
 
 struct cyl_heat_s {
     cyl_plan_t plan = nullptr;
+    hipStream_t stream = nullptr;   // copy of the plan's stream: destroy needs no parent handle
     std::unique_ptr<Setup> setup;
     double alpha = 0, dt = 0, kappa = 0, tol = 0;
     int order = 1;
@@ -156,6 +157,7 @@ struct cyl_heat_s {
 // segment being differentiated, and the adjoint work buffers.
 struct cyl_heat_grad_s {
     cyl_heat_t heat = nullptr;
+    hipStream_t stream = nullptr;       // copy of the plan's stream (see cyl_heat_s)
     int steps = 0, every = 0, nseg = 0;
     int seg_holds = -1;                 // segment whose solutions X_k are in seg
     bool ready = false;                 // a forward run has filled the checkpoints
@@ -681,6 +683,7 @@ int cyl_heat_create(cyl_heat_t* h, cyl_plan_t plan, double alpha, double dt, int
         const Geometry& geo = pl->geo;
         auto H = std::make_unique<cyl_heat_s>();
         H->plan = pl;
+        H->stream = pl->stream;
         H->alpha = alpha; H->dt = dt; H->order = bdf_order; H->tol = adi_tol;
         if (bdf_order == 1) { H->kappa = dt; H->beta[0] = 1.0; }
         else {
@@ -797,7 +800,7 @@ int cyl_heat_read(cyl_heat_t h, int space, double* T_out) {
 int cyl_heat_destroy(cyl_heat_t h) {
     return guarded([&] {
         if (!h) fail(CYL_E_INVALID_ARG, "heat handle is NULL");
-        (void)hipStreamSynchronize(h->plan->stream);
+        (void)hipStreamSynchronize(h->stream);
         delete h;
     });
 }
@@ -885,6 +888,7 @@ int cyl_heat_grad_create(cyl_heat_grad_t* out, cyl_heat_t h, int n_steps, int ch
         const Geometry& g = pl->geo;
         auto a = std::make_unique<cyl_heat_grad_s>();
         a->heat = h;
+        a->stream = pl->stream;
         a->steps = n_steps;
         a->every = std::min(checkpoint_every, n_steps);
         a->nseg = (n_steps + a->every - 1) / a->every;
@@ -1021,7 +1025,7 @@ int cyl_heat_grad_backward(cyl_heat_grad_t a, int space, const double* T_bar, do
 int cyl_heat_grad_destroy(cyl_heat_grad_t a) {
     return guarded([&] {
         if (!a) fail(CYL_E_INVALID_ARG, "handle is NULL");
-        (void)hipStreamSynchronize(a->heat->plan->stream);
+        (void)hipStreamSynchronize(a->stream);
         delete a;
     });
 }

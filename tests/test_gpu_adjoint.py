@@ -214,3 +214,23 @@ def test_d192_alpha_gradient_closed_form_on_eigenmode():
     ref0 = 2 * c ** (2 * steps) * nrm
     got0 = float(torch.sum(T0b * dev(phi)))
     assert abs(got0 - ref0) <= 1e-9 * ref0
+
+
+def test_handles_can_be_destroyed_in_any_order():
+    """Destroying a parent handle first (as Python's cycle collector may do)
+    leaves the child's destroy call safe."""
+    need_gpu()
+    m, n, p = 10, 9, 4
+    banner("destroy order")
+    T0 = smooth_values(m, n, p, S + 94)
+    plan = cyl.Plan(m, n, p)
+    H = cyl.Heat(plan, [dev(T0)], dev(T0), 1.0, 1e-2, 1, 1e-12)
+    G = cyl.HeatGrad(H, 2, 1)
+    G.forward()
+    H.close()
+    G.close()
+    plan2 = cyl.Plan(m, n, p)
+    H2 = cyl.Heat(plan2, [dev(T0)], dev(T0), 1.0, 1e-2, 1, 1e-12)
+    plan2.close()
+    H2.close()
+    plan.close()
