@@ -32,6 +32,8 @@ namespace {
 constexpr int G = 8;          // rows per software-pipelined group
 constexpr int kRRec = 12;
 constexpr int kZRec = 8;
+constexpr int kRCouple = 3;   // record rows after a block's r records (5 x 5 coupling)
+constexpr int kZCouple = 2;   // record rows after a block's z records (3 x 3 coupling)
 
 // ---------------------------------------------------------------------------
 // LDS-resident sweeps with a compile-time row stride LD (so every row offset
@@ -266,6 +268,505 @@ void k_adi_lds(const BlockDesc* __restrict__ blocks, const double* __restrict__ 
     extern __shared__ double sm[];
     const BlockDesc bd = blocks[blockIdx.x];
     adi_block_lds<NP + 1>(sm, bd, E, X, rtab, ztab, vmu, accumulate);
+}
+
+// ---------------------------------------------------------------------------
+// Split sweeps: two threads per line, so that a block whose state fills the
+// LDS of a CU still keeps all four SIMDs busy.  A line of n unknowns is cut
+// at the split row t (a multiple of G): threads [0, L) eliminate [0, t)
+// downwards with the LU records, threads [L, 2L) eliminate [t, n) upwards
+// with the UL records; both exchange their last values through the LDS
+// exchange area, solve the small coupling system for the unknowns around t,
+// and substitute outwards from t.  Bands: r-pass (lo, hi) = (2, 3), coupling
+// x_{t-2} .. x_{t+2}; z-pass (1, 2), coupling x_{t-1} .. x_{t+1}.
+// ---------------------------------------------------------------------------
+
+// Barrier for LDS traffic only: records streamed into LDS by the other half of
+// the iteration and right-hand-side prefetches may stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// r-pass, rows [0, t) of column k (LU records).  pre: W rows t, t+1, t+2 of
+// this column, read before any thread overwrote them.  Returns g_{t-2}, g_{t-1}.
+template <int LD>
+__device__ __forceinline__ void rs_top_fwd(double* __restrict__ S, int t, int k,
+                                           const double* __restrict__ RC,
+                                           const double* __restrict__ Ecol, double vmu,
+                                           const double pre[3], double* gt2, double* gt1) {
+    const double2* E2 = reinterpret_cast<const double2*>(Ecol);
+    double* Sk = S + k;
+    double wv[14];                 // rows i0-2 .. i0+11 of W
+    wv[0] = 0.0; wv[1] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wv[2 + q] = Sk[q * LD];
+    double2 eb[G / 2], en[G / 2];
+#pragma unroll
+    for (int q = 0; q < G / 2; ++q) { eb[q] = E2[q]; en[q] = E2[G / 2 + q]; }
+    double g1 = 0.0, g2 = 0.0;
+    for (int i0 = 0; i0 < t; i0 += G) {
+        double* Sg = Sk + i0 * LD;
+        const double2* Rg = reinterpret_cast<const double2*>(RC + i0 * kRRec);
+        double c[G][8];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double2 v = Rg[q * (kRRec / 2) + s];
+                c[q][2 * s] = v.x;
+                c[q][2 * s + 1] = v.y;
+            }
+        if (i0 + G < t) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) wv[6 + q] = Sg[(4 + q) * LD];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) wv[6 + q] = Sg[(4 + q) * LD];
+            wv[10] = pre[0]; wv[11] = pre[1]; wv[12] = pre[2]; wv[13] = 0.0;
+        }
+        double2 enn[G / 2];
+#pragma unroll
+        for (int q = 0; q < G / 2; ++q) enn[q] = E2[(i0 + 2 * G) / 2 + q];
+        double e[G];
+#pragma unroll
+        for (int q = 0; q < G / 2; ++q) { e[2 * q] = eb[q].x; e[2 * q + 1] = eb[q].y; }
+        double h[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            h[q] = c[q][0] * wv[q] + c[q][1] * wv[q + 1] + c[q][2] * wv[q + 2] +
+                   c[q][3] * wv[q + 3] + c[q][4] * wv[q + 4] + c[q][5] * wv[q + 5] - vmu * e[q];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double tq = h[q] - c[q][6] * g2;
+            const double g = tq - c[q][7] * g1;
+            Sg[q * LD] = g;
+            g2 = g1;
+            g1 = g;
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) wv[q] = wv[8 + q];
+#pragma unroll
+        for (int q = 0; q < G / 2; ++q) { eb[q] = en[q]; en[q] = enn[q]; }
+    }
+    *gt2 = g2;
+    *gt1 = g1;
+}
+
+// r-pass back substitution on rows t-1 .. 0, starting from x_t, x_{t+1}, x_{t+2}.
+template <int LD>
+__device__ __forceinline__ void rs_top_bwd(double* __restrict__ S, int t, int k,
+                                           const double* __restrict__ RC, double z1, double z2,
+                                           double z3) {
+    double* Sk = S + k;
+    double gb[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) gb[q] = Sk[(t - G + q) * LD];
+    for (int i0 = t - G; i0 >= 0; i0 -= G) {
+        double* Sg = Sk + i0 * LD;
+        const double2* Rg = reinterpret_cast<const double2*>(RC + i0 * kRRec + 8);
+        double c[G][4];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const double2 v = Rg[q * (kRRec / 2) + s];
+                c[q][2 * s] = v.x;
+                c[q][2 * s + 1] = v.y;
+            }
+        double gn[G];
+        if (i0 > 0) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) gn[q] = Sg[(q - G) * LD];
+        }
+#pragma unroll
+        for (int q = G - 1; q >= 0; --q) {
+            const double tq = c[q][0] * gb[q] - c[q][3] * z3 - c[q][2] * z2;
+            const double z = tq - c[q][1] * z1;
+            Sg[q * LD] = z;
+            z3 = z2; z2 = z1; z1 = z;
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) gb[q] = gn[q];
+    }
+}
+
+// r-pass, rows mp-1 .. t of column k (UL records, upwards).  preb: W rows
+// t-2, t-1 of this column.  Returns g'_t, g'_{t+1}, g'_{t+2}.
+template <int LD>
+__device__ __forceinline__ void rs_bot_fwd(double* __restrict__ S, int mp, int t, int k,
+                                           const double* __restrict__ RC,
+                                           const double* __restrict__ Ecol, double vmu,
+                                           const double preb[2], double* g0, double* g1,
+                                           double* g2) {
+    const double2* E2 = reinterpret_cast<const double2*>(Ecol);
+    double* Sk = S + k;
+    double up[3] = {0.0, 0.0, 0.0};        // old W rows i0+8 .. i0+10
+    double gp1 = 0.0, gp2 = 0.0, gp3 = 0.0;  // g'_{i+1}, g'_{i+2}, g'_{i+3}
+    double2 eb[G / 2], en[G / 2];
+#pragma unroll
+    for (int q = 0; q < G / 2; ++q) { eb[q] = E2[(mp - G) / 2 + q]; en[q] = E2[(mp - 2 * G) / 2 + q]; }
+    for (int i0 = mp - G; i0 >= t; i0 -= G) {
+        double* Sg = Sk + i0 * LD;
+        const double2* Rg = reinterpret_cast<const double2*>(RC + i0 * kRRec);
+        double c[G][10];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+                const double2 v = Rg[q * (kRRec / 2) + s];
+                c[q][2 * s] = v.x;
+                c[q][2 * s + 1] = v.y;
+            }
+        double w[13];                      // rows i0-2 .. i0+10 of W
+        if (i0 > t) {
+            w[0] = Sg[-2 * LD];
+            w[1] = Sg[-LD];
+        } else {
+            w[0] = preb[0];
+            w[1] = preb[1];
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) w[2 + q] = Sg[q * LD];
+        w[10] = up[0]; w[11] = up[1]; w[12] = up[2];
+        double2 enn[G / 2];
+        if (i0 >= 2 * G) {
+#pragma unroll
+            for (int q = 0; q < G / 2; ++q) enn[q] = E2[(i0 - 2 * G) / 2 + q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < G / 2; ++q) enn[q] = make_double2(0.0, 0.0);
+        }
+        double e[G];
+#pragma unroll
+        for (int q = 0; q < G / 2; ++q) { e[2 * q] = eb[q].x; e[2 * q + 1] = eb[q].y; }
+        double h[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            h[q] = c[q][0] * w[q] + c[q][1] * w[q + 1] + c[q][2] * w[q + 2] +
+                   c[q][3] * w[q + 3] + c[q][4] * w[q + 4] + c[q][5] * w[q + 5] - vmu * e[q];
+#pragma unroll
+        for (int q = G - 1; q >= 0; --q) {
+            const double tq = h[q] - c[q][8] * gp3 - c[q][7] * gp2;
+            const double g = tq - c[q][6] * gp1;
+            Sg[q * LD] = g;
+            gp3 = gp2; gp2 = gp1; gp1 = g;
+        }
+        up[0] = w[2]; up[1] = w[3]; up[2] = w[4];
+#pragma unroll
+        for (int q = 0; q < G / 2; ++q) { eb[q] = en[q]; en[q] = enn[q]; }
+    }
+    *g0 = gp1;
+    *g1 = gp2;
+    *g2 = gp3;
+}
+
+// r-pass forward substitution on rows t .. mp-1, starting from x_{t-1}, x_{t-2}.
+template <int LD>
+__device__ __forceinline__ void rs_bot_bwd(double* __restrict__ S, int mp, int t, int k,
+                                           const double* __restrict__ RC, double xm1, double xm2) {
+    double* Sk = S + k;
+    double gb[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) gb[q] = Sk[(t + q) * LD];
+    for (int i0 = t; i0 < mp; i0 += G) {
+        double* Sg = Sk + i0 * LD;
+        const double2* Rg = reinterpret_cast<const double2*>(RC + i0 * kRRec + 8);
+        double c[G][3];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double2 a = Rg[q * (kRRec / 2)], b = Rg[q * (kRRec / 2) + 1];
+            c[q][0] = a.y; c[q][1] = b.x; c[q][2] = b.y;     // dinv', L^(i,i-1), L^(i,i-2)
+        }
+        double gn[G];
+        if (i0 + G < mp) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) gn[q] = Sg[(G + q) * LD];
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double tq = c[q][0] * gb[q] - c[q][2] * xm2;
+            const double x = tq - c[q][1] * xm1;
+            Sg[q * LD] = x;
+            xm2 = xm1; xm1 = x;
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) gb[q] = gn[q];
+    }
+}
+
+// z-pass, columns [0, t) of one row (LU records).  Returns g_{t-1}.
+__device__ __forceinline__ double zs_top_fwd(double* __restrict__ row, int t,
+                                             const double* __restrict__ ZC) {
+    double zb[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) zb[q] = row[q];
+    double gp = 0.0;
+    for (int k0 = 0; k0 < t; k0 += G) {
+        double* rg = row + k0;
+        double l[G], zn[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) l[q] = ZC[(k0 + q) * kZRec];
+#pragma unroll
+        for (int q = 0; q < G; ++q) zn[q] = rg[G + q];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double g = zb[q] - l[q] * gp;
+            rg[q] = g;
+            gp = g;
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) zb[q] = zn[q];
+    }
+    return gp;
+}
+
+// z-pass back substitution on columns t-1 .. 0 from x_t, x_{t+1}; unless this
+// is the last iteration, each x is replaced by w = x (u' B + D) on the fly
+// (columns < t only).
+template <bool kLast>
+__device__ __forceinline__ void zs_top_bwd(double* __restrict__ row, int t,
+                                           const double* __restrict__ ZC, double x1, double x2) {
+    double gb[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) gb[q] = row[t - G + q];
+    double x3 = 0.0;
+    double pn[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = t - G; k0 >= 0; k0 -= G) {
+        double* rg = row + k0;
+        const double2* zg = reinterpret_cast<const double2*>(ZC + k0 * kZRec);
+        double c[G][3], pr[G][4];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double2 a = zg[q * (kZRec / 2) + 0], b = zg[q * (kZRec / 2) + 1];
+            const double2 d = zg[q * (kZRec / 2) + 2], e = zg[q * (kZRec / 2) + 3];
+            c[q][0] = a.y; c[q][1] = b.x; c[q][2] = b.y;
+            pr[q][0] = d.x; pr[q][1] = d.y; pr[q][2] = e.x; pr[q][3] = e.y;
+        }
+        double gn[G];
+        if (k0 > 0) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) gn[q] = rg[q - G];
+        }
+#pragma unroll
+        for (int q = G - 1; q >= 0; --q) {
+            const double x = c[q][0] * gb[q] - c[q][2] * x2 - c[q][1] * x1;
+            if (kLast) {
+                rg[q] = x;
+            } else {
+                const double* p = (q == G - 1) ? pn : pr[q + 1];
+                if (q < G - 1 || k0 + G < t)
+                    rg[q + 1] = p[0] * x + p[1] * x1 + p[2] * x2 + p[3] * x3;
+            }
+            x3 = x2; x2 = x1; x1 = x;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) pn[s] = pr[0][s];
+#pragma unroll
+        for (int q = 0; q < G; ++q) gb[q] = gn[q];
+    }
+    if (!kLast) row[0] = pn[1] * x1 + pn[2] * x2 + pn[3] * x3;
+}
+
+// z-pass, columns np-1 .. t of one row (UL records, leftwards).  Returns
+// g'_t, g'_{t+1}.
+__device__ __forceinline__ void zs_bot_fwd(double* __restrict__ row, int np, int t,
+                                           const double* __restrict__ ZC, double* g0,
+                                           double* g1) {
+    double zb[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) zb[q] = row[np - G + q];
+    double gp1 = 0.0, gp2 = 0.0;
+    for (int k0 = np - G; k0 >= t; k0 -= G) {
+        double* rg = row + k0;
+        double u1[G], u2[G], zn[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double2 u = *reinterpret_cast<const double2*>(ZC + (k0 + q) * kZRec);
+            u1[q] = u.x; u2[q] = u.y;
+        }
+        if (k0 - G >= t) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) zn[q] = rg[q - G];
+        }
+#pragma unroll
+        for (int q = G - 1; q >= 0; --q) {
+            const double g = zb[q] - u2[q] * gp2 - u1[q] * gp1;
+            rg[q] = g;
+            gp2 = gp1; gp1 = g;
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) zb[q] = zn[q];
+    }
+    *g0 = gp1;
+    *g1 = gp2;
+}
+
+// z-pass forward substitution on columns t .. np-1 from x_{t-1}; unless this
+// is the last iteration, w_{k-2} = x (u' B + D) at column k-2 >= t is written
+// as soon as x_k is known, and the last two columns after the loop.
+template <bool kLast>
+__device__ __forceinline__ void zs_bot_bwd(double* __restrict__ row, int np, int t,
+                                           const double* __restrict__ ZC, double xm1) {
+    double gb[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) gb[q] = row[t + q];
+    double xm2 = 0.0, xm3 = 0.0;
+    for (int k0 = t; k0 < np; k0 += G) {
+        double* rg = row + k0;
+        double c[G][2], pr[G][4];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double2 a = *reinterpret_cast<const double2*>(ZC + (k0 + q) * kZRec + 2);
+            c[q][0] = a.x; c[q][1] = a.y;                      // dinv', L^(k, k-1)
+            if (!kLast) {
+                const double2* p = reinterpret_cast<const double2*>(ZC + (k0 + q - 2) * kZRec + 4);
+                const double2 d = p[0], e = p[1];
+                pr[q][0] = d.x; pr[q][1] = d.y; pr[q][2] = e.x; pr[q][3] = e.y;
+            }
+        }
+        double gn[G];
+        if (k0 + G < np) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) gn[q] = rg[G + q];
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double x = c[q][0] * gb[q] - c[q][1] * xm1;
+            if (kLast) {
+                rg[q] = x;
+            } else if (k0 + q - 2 >= t) {
+                rg[q - 2] = pr[q][0] * xm3 + pr[q][1] * xm2 + pr[q][2] * xm1 + pr[q][3] * x;
+            }
+            xm3 = xm2; xm2 = xm1; xm1 = x;
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) gb[q] = gn[q];
+    }
+    if (!kLast) {
+        const double2* pa = reinterpret_cast<const double2*>(ZC + (np - 2) * kZRec + 4);
+        const double2* pb = reinterpret_cast<const double2*>(ZC + (np - 1) * kZRec + 4);
+        const double2 a0 = pa[0], a1 = pa[1], b0 = pb[0];
+        row[np - 2] = a0.x * xm3 + a0.y * xm2 + a1.x * xm1;
+        row[np - 1] = b0.x * xm2 + b0.y * xm1;
+    }
+}
+
+// One workgroup (2 L threads) per parity block, all J iterations in LDS.
+// LDS: state (mp rows of LD), r records (+ coupling), z records (+ coupling),
+// exchange area (5 x L).
+template <int LD>
+__device__ __forceinline__ void adi_block_split(double* sm, const BlockDesc& bd,
+                                                const double* __restrict__ E, double* X,
+                                                const double* __restrict__ rtab,
+                                                const double* __restrict__ ztab,
+                                                const double* __restrict__ vmu, int accumulate) {
+    const int me = bd.me, ne = bd.ne, mp = bd.mp, np = bd.np, tr = bd.tr, tz = bd.tz;
+    const int tid = threadIdx.x, nt = blockDim.x, L = nt >> 1;
+    const int line = tid % L;
+    const bool top = tid < L;
+    double* S = sm;
+    const int nr = (mp + kRCouple) * kRRec, nz = (np + kZCouple) * kZRec;
+    double* RCs = S + mp * LD;
+    double* ZCs = RCs + lds_chunks(nr);
+    double* XC = ZCs + lds_chunks(nz);
+    for (int idx = tid; idx < mp * LD; idx += nt) S[idx] = 0.0;
+    copy_to_lds(RCs, rtab + bd.rbase, nr);
+    copy_to_lds(ZCs, ztab + bd.zbase, nz);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const double* Ecol = E + bd.eoff + static_cast<int64_t>(line) * mp;
+    for (int j = 0; j < bd.J; ++j) {
+        const double vm = vmu[bd.soff + j];
+        // ---- r-pass: lines are columns
+        double pre[3] = {0.0, 0.0, 0.0};
+        if (line < ne) {
+            if (top) {
+#pragma unroll
+                for (int s = 0; s < 3; ++s) pre[s] = S[(tr + s) * LD + line];
+            } else {
+#pragma unroll
+                for (int s = 0; s < 2; ++s) pre[s] = S[(tr - 2 + s) * LD + line];
+            }
+        }
+        lds_barrier();
+        if (line < ne) {
+            if (top) {
+                double a, b;
+                rs_top_fwd<LD>(S, tr, line, RCs, Ecol, vm, pre, &a, &b);
+                XC[line] = a;
+                XC[L + line] = b;
+            } else {
+                double a, b, c;
+                rs_bot_fwd<LD>(S, mp, tr, line, RCs, Ecol, vm, pre, &a, &b, &c);
+                XC[2 * L + line] = a;
+                XC[3 * L + line] = b;
+                XC[4 * L + line] = c;
+            }
+        }
+        lds_barrier();
+        if (line < ne) {
+            double v[5], y[5];
+#pragma unroll
+            for (int s = 0; s < 5; ++s) v[s] = XC[s * L + line];
+            const double* K5 = RCs + mp * kRRec;
+#pragma unroll
+            for (int r = 0; r < 5; ++r)
+                y[r] = K5[5 * r] * v[0] + K5[5 * r + 1] * v[1] + K5[5 * r + 2] * v[2] +
+                       K5[5 * r + 3] * v[3] + K5[5 * r + 4] * v[4];
+            if (top) rs_top_bwd<LD>(S, tr, line, RCs, y[2], y[3], y[4]);
+            else rs_bot_bwd<LD>(S, mp, tr, line, RCs, y[1], y[0]);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        const bool more = j + 1 < bd.J;
+        if (more) copy_to_lds(RCs, rtab + bd.rbase + (j + 1) * bd.rstride, nr);
+        // ---- z-pass: lines are rows
+        double* row = S + line * LD;
+        if (line < me) {
+            if (top) {
+                XC[line] = zs_top_fwd(row, tz, ZCs);
+            } else {
+                double a, b;
+                zs_bot_fwd(row, np, tz, ZCs, &a, &b);
+                XC[L + line] = a;
+                XC[2 * L + line] = b;
+            }
+        }
+        lds_barrier();
+        if (line < me) {
+            const double v0 = XC[line], v1 = XC[L + line], v2 = XC[2 * L + line];
+            const double* K3 = ZCs + np * kZRec;
+            const double y0 = K3[0] * v0 + K3[1] * v1 + K3[2] * v2;
+            const double y1 = K3[3] * v0 + K3[4] * v1 + K3[5] * v2;
+            const double y2 = K3[6] * v0 + K3[7] * v1 + K3[8] * v2;
+            if (top) {
+                if (more) zs_top_bwd<false>(row, tz, ZCs, y1, y2);
+                else zs_top_bwd<true>(row, tz, ZCs, y1, y2);
+            } else {
+                if (more) zs_bot_bwd<false>(row, np, tz, ZCs, y0);
+                else zs_bot_bwd<true>(row, np, tz, ZCs, y0);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (more) copy_to_lds(ZCs, ztab + bd.zbase + (j + 1) * bd.zstride, nz);
+    }
+    double* Xb = X + bd.xoff;
+    for (int idx = tid; idx < me * ne; idx += nt) {
+        const int i = idx / ne, k = idx - i * ne;
+        const double v = S[i * LD + k];
+        Xb[idx] = accumulate ? Xb[idx] + v : v;
+    }
+}
+
+template <int NP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_adi_split(const BlockDesc* __restrict__ blocks, const double* __restrict__ E, double* X,
+                 const double* __restrict__ rtab, const double* __restrict__ ztab,
+                 const double* __restrict__ vmu, int accumulate) {
+    extern __shared__ double sm[];
+    const BlockDesc bd = blocks[blockIdx.x];
+    adi_block_split<NP + 1>(sm, bd, E, X, rtab, ztab, vmu, accumulate);
 }
 
 // ---------------------------------------------------------------------------
@@ -585,6 +1086,21 @@ hipError_t set_limit(size_t bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
 
+template <int NP>
+hipError_t launch_split(const BlockDesc* blocks, int nblocks, int threads, const double* E,
+                        double* X, const double* rtab, const double* ztab, const double* vmu,
+                        bool accumulate, size_t lds_bytes, hipStream_t s) {
+    hipLaunchKernelGGL(k_adi_split<NP>, dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
+                       rtab, ztab, vmu, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <int NP>
+hipError_t set_split_limit(size_t bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_split<NP>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+}
+
 }  // namespace
 
 #define CYL_NP_CASES(X) X(8) X(16) X(24) X(32) X(40) X(48) X(56) X(64) X(72) X(80) X(88) X(96) \
@@ -605,6 +1121,34 @@ hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, int np0
     hipLaunchKernelGGL(k_adi_global, dim3(nblocks), dim3(threads), 0, s, blocks, E, X, state,
                        state_stride, rtab, ztab, vmu, accumulate ? 1 : 0);
     return hipGetLastError();
+}
+
+size_t adi_split_lds_bytes(int mp0, int np0) {
+    auto chunks = [](int x) { return static_cast<size_t>((x + 127) / 128 * 128); };
+    const size_t doubles = static_cast<size_t>(mp0) * (np0 + 1) + chunks((mp0 + kRCouple) * kRRec) +
+                           chunks((np0 + kZCouple) * kZRec) + 5 * 128;
+    return doubles * sizeof(double);
+}
+
+hipError_t launch_adi_split(const BlockDesc* blocks, int nblocks, int threads, int np0,
+                            const double* E, double* X, const double* rtab, const double* ztab,
+                            const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s) {
+    if (threads < 128 || threads > 256 || threads % 128 != 0) return hipErrorInvalidValue;
+    switch (np0) {
+#define CYL_CASE(v) case v: return launch_split<v>(blocks, nblocks, threads, E, X, rtab, ztab, vmu, accumulate, lds_bytes, s);
+        CYL_NP_CASES(CYL_CASE)
+#undef CYL_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t adi_split_set_lds_limit(int np0, size_t bytes) {
+    switch (np0) {
+#define CYL_CASE(v) case v: return set_split_limit<v>(bytes);
+        CYL_NP_CASES(CYL_CASE)
+#undef CYL_CASE
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t adi_set_lds_limit(int np0, size_t bytes) {

@@ -130,6 +130,7 @@ struct cyl_plan_s {
     DevMem plane_of, ztabA, atab_proj;
     DevMem planesA, planesB, E, X, R, state, acc;
     bool use_lds = false;
+    bool adi_split = false;        // split-sweep kernel (two threads per line)
     int64_t state_stride = 0;
     int adi_threads = 64;
     size_t lds_bytes = 0;
@@ -272,7 +273,7 @@ std::unique_ptr<Setup> make_setup(cyl_plan_t pl, double ka, double eps, bool fli
     auto s = std::make_unique<Setup>();
     double eps_pass;
     pass_policy(pl->m, pl->n, eps, &s->passes, &eps_pass);
-    s->h = build_adi_setup(pl->geo, pl->rops, pl->zops, ka, eps_pass, flip);
+    s->h = build_adi_setup(pl->geo, pl->rops, pl->zops, ka, eps_pass, flip, pl->adi_split);
     s->flip = flip;
     const Geometry& g = pl->geo;
     const int me0 = g.me[0], me1 = g.me[1], ne0 = g.ne[0], ne1 = g.ne[1];
@@ -292,10 +293,12 @@ std::unique_ptr<Setup> make_setup(cyl_plan_t pl, double ka, double eps, bool fli
                 b.pr = pr; b.pz = pz; b.part = g.plane_part[pl_i]; b.plane = pl_i;
                 b.eoff = pl_i * g.eplane_elems + eblk[2 * pr + pz];
                 b.xoff = pl_i * g.plane_elems + xblk[2 * pr + pz];
-                b.rstride = static_cast<int64_t>(g.mp[0] + g.mp[1]) * kRRec;
-                b.zstride = static_cast<int64_t>(g.np[0] + g.np[1]) * kZRec;
-                b.rbase = s->h.roff[w] + (pr ? static_cast<int64_t>(g.mp[0]) * kRRec : 0);
-                b.zbase = s->h.zoff[w] + (pz ? static_cast<int64_t>(g.np[0]) * kZRec : 0);
+                b.rstride = static_cast<int64_t>(s->h.rrows[0] + s->h.rrows[1]) * kRRec;
+                b.zstride = static_cast<int64_t>(s->h.zrows[0] + s->h.zrows[1]) * kZRec;
+                b.rbase = s->h.roff[w] + (pr ? static_cast<int64_t>(s->h.rrows[0]) * kRRec : 0);
+                b.zbase = s->h.zoff[w] + (pz ? static_cast<int64_t>(s->h.zrows[0]) * kZRec : 0);
+                b.tr = s->h.tr[pr];
+                b.tz = s->h.tz[pz];
                 b.soff = s->h.soff[w];
                 s->hblocks.push_back(b);
             }
@@ -412,11 +415,17 @@ void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X) {
             rhs = pl->R.as<double>();
         }
         Scope sc(pl, PH_ADI);
-        hip_check(launch_adi(s->blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
-                             pl->state.as<double>(), pl->state_stride, s->rtab.as<double>(),
-                             s->ztab.as<double>(),
-                             s->vmu.as<double>(), pass > 0, pl->use_lds, pl->lds_bytes, pl->stream),
-                  "adi");
+        if (pl->adi_split)
+            hip_check(launch_adi_split(s->blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
+                                       s->rtab.as<double>(), s->ztab.as<double>(), s->vmu.as<double>(),
+                                       pass > 0, pl->lds_bytes, pl->stream),
+                      "adi");
+        else
+            hip_check(launch_adi(s->blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
+                                 pl->state.as<double>(), pl->state_stride, s->rtab.as<double>(),
+                                 s->ztab.as<double>(),
+                                 s->vmu.as<double>(), pass > 0, pl->use_lds, pl->lds_bytes, pl->stream),
+                      "adi");
     }
 }
 
@@ -534,6 +543,22 @@ void build_plan(cyl_plan_t pl) {
             pl->use_lds = false;
         }
     }
+    // split sweeps (two threads per line) when every parity block is long enough
+    if (env_int("CYLSPEC_ADI_SPLIT", 1) != 0 && mode == 0 && g.np[0] <= 128 && g.mp[0] <= 128 &&
+        adi_split_fits(std::min(g.me[0], g.me[1]), std::min(g.ne[0], g.ne[1]))) {
+        const size_t sb = adi_split_lds_bytes(g.mp[0], g.np[0]);
+        bool ok = sb <= static_cast<size_t>(max_lds);
+        if (ok && sb > 65536 && adi_split_set_lds_limit(g.np[0], sb) != hipSuccess) {
+            (void)hipGetLastError();
+            ok = false;
+        }
+        if (ok) {
+            pl->adi_split = true;
+            pl->adi_threads = 2 * (((std::max(g.me[0], g.ne[0]) + 63) / 64) * 64);
+            pl->lds_bytes = sb;
+            pl->use_lds = true;
+        }
+    }
     if (!pl->use_lds) {
         pl->adi_threads = std::min(512, pl->adi_threads);
         pl->state.alloc(static_cast<size_t>(4 * g.nplanes) * pl->state_stride * sizeof(double));
@@ -541,7 +566,8 @@ void build_plan(cyl_plan_t pl) {
     if (env_int("CYLSPEC_LOG", 0) > 0)
         std::fprintf(stderr, "[cylspec] plan %dx%dx%d: blocks me=(%d,%d) ne=(%d,%d), ADI %s, %d threads, "
                              "LDS %zu of %d bytes, DFT Nb r/z/theta = %d/%d/%d\n",
-                     m, n, p, g.me[0], g.me[1], g.ne[0], g.ne[1], pl->use_lds ? "LDS-resident" : "HBM-resident",
+                     m, n, p, g.me[0], g.me[1], g.ne[0], g.ne[1],
+                     pl->adi_split ? "LDS-resident split" : pl->use_lds ? "LDS-resident" : "HBM-resident",
                      pl->adi_threads, pl->lds_bytes, max_lds, pl->dr.t.Nb, pl->dz.t.Nb, pl->dth.t.Nb);
 }
 

@@ -30,6 +30,7 @@ struct BlockDesc {
     int w, J, me, ne;
     int mp, np;              // me, ne rounded up to multiples of 8
     int pr, pz, part, plane;
+    int tr, tz;              // split rows of the two-thread sweeps (0: not split)
     int64_t eoff, xoff;
     int64_t rbase, zbase;    // offset of (j = 0) records in rtab / ztab
     int64_t rstride, zstride;// record stride between successive shifts
@@ -74,9 +75,18 @@ hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, int np0
                       double* X, double* state, int64_t state_stride, const double* rtab,
                       const double* ztab, const double* vmu, bool accumulate, bool use_lds,
                       size_t lds_bytes, hipStream_t s);
+// Split-sweep LDS-resident ADI (tables built with the split layout): two
+// threads per line, 2 * lines threads per workgroup (lines a multiple of 64,
+// at most 128).
+hipError_t launch_adi_split(const BlockDesc* blocks, int nblocks, int threads, int np0,
+                            const double* E, double* X, const double* rtab, const double* ztab,
+                            const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s);
+// LDS bytes of the split kernel for padded block sizes mp0 x np0.
+size_t adi_split_lds_bytes(int mp0, int np0);
 
-// Raise the dynamic-LDS limit of the LDS-resident ADI kernel for width np0.
+// Raise the dynamic-LDS limit of the LDS-resident ADI kernels for width np0.
 hipError_t adi_set_lds_limit(int np0, size_t bytes);
+hipError_t adi_split_set_lds_limit(int np0, size_t bytes);
 
 // out = sE * E - sAB * (A X B) - sCD * (C X D) blockwise.  atab: per (w, r
 // parity) rows of 12 (A row i at i-2..i+3, then C row i at i-2..i+3), w stride

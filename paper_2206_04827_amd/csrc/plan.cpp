@@ -453,7 +453,86 @@ void nopivot_lu(const Band& M, std::vector<double>& L, std::vector<double>& dinv
     }
 }
 
+// No-pivot UL of M (eliminating the upper band from the last row up):
+// M = U' L' with U' unit upper (hi multipliers per row) and L' lower.  Per row:
+// Up = U'(i, i+t) for t = 1..hi, dinv = 1 / L'(i, i), Ls = dinv L'(i, i-t) for t = 1..lo.
+void nopivot_ul(const Band& M, std::vector<double>& Up, std::vector<double>& dinv,
+                std::vector<double>& Ls) {
+    const int n = M.rows, lo = M.lo, hi = M.hi;
+    std::vector<double> a(static_cast<size_t>(n) * (lo + hi + 1));
+    auto at = [&](int i, int j) -> double& { return a[static_cast<size_t>(i) * (lo + hi + 1) + (j - i + lo)]; };
+    for (int i = 0; i < n; ++i)
+        for (int j = std::max(0, i - lo); j <= std::min(n - 1, i + hi); ++j) at(i, j) = M.get(i, j);
+    for (int k = n - 1; k >= 0; --k) {
+        const double piv = at(k, k);
+        if (!(std::fabs(piv) > 0.0) || !std::isfinite(piv)) throw std::runtime_error("zero pivot in ADI factorisation");
+        for (int i = k - 1; i >= std::max(0, k - hi); --i) {
+            const double f = at(i, k) / piv;
+            at(i, k) = f;
+            for (int j = std::max(0, k - lo); j < k; ++j) at(i, j) -= f * at(k, j);
+        }
+    }
+    Up.assign(static_cast<size_t>(n) * hi, 0.0);
+    dinv.assign(n, 0.0);
+    Ls.assign(static_cast<size_t>(n) * lo, 0.0);
+    for (int i = 0; i < n; ++i) {
+        for (int t = 1; t <= hi; ++t) if (i + t < n) Up[static_cast<size_t>(i) * hi + (t - 1)] = at(i, i + t);
+        dinv[i] = 1.0 / at(i, i);
+        for (int t = 1; t <= lo; ++t) if (i - t >= 0) Ls[static_cast<size_t>(i) * lo + (t - 1)] = dinv[i] * at(i, i - t);
+    }
+}
+
+// Coupling of the split sweeps for a line of bandwidths (lo, hi) cut at t:
+// the unknowns x_{t-lo} .. x_{t+hi-1} satisfy the normalised last lo rows of
+// the LU part and first hi rows of the UL part,
+//   x_i + sum_s dinv_i U_{i,i+s} x_{i+s} = dinv_i g_i        (t-lo <= i < t)
+//   x_i + sum_s dinv'_i L'_{i,i-s} x_{i-s} = dinv'_i g'_i    (t <= i < t+hi),
+// so x = K (g_{t-lo}, .., g_{t-1}, g'_t, .., g'_{t+hi-1}) with
+// K = C^-1 diag(dinv, dinv').  K is written row-major (K x K doubles).
+void split_coupling(int lo, int hi, int t, const std::vector<double>& Us, const std::vector<double>& dinv,
+                    const std::vector<double>& Ls, const std::vector<double>& dinvp, double* out) {
+    const int K = lo + hi, x0 = t - lo;
+    std::vector<long double> C(static_cast<size_t>(K) * K, 0.0L), inv(static_cast<size_t>(K) * K, 0.0L);
+    std::vector<long double> d(K);
+    for (int r = 0; r < K; ++r) {
+        const int i = x0 + r;
+        C[r * K + r] = 1.0L;
+        if (i < t) {
+            for (int s = 1; s <= hi; ++s) C[r * K + (r + s)] = Us[static_cast<size_t>(i) * hi + (s - 1)];
+            d[r] = dinv[i];
+        } else {
+            for (int s = 1; s <= lo; ++s) C[r * K + (r - s)] = Ls[static_cast<size_t>(i) * lo + (s - 1)];
+            d[r] = dinvp[i];
+        }
+        inv[r * K + r] = 1.0L;
+    }
+    for (int c = 0; c < K; ++c) {                 // Gauss-Jordan, partial pivoting
+        int p = c;
+        for (int r = c + 1; r < K; ++r) if (std::fabs(C[r * K + c]) > std::fabs(C[p * K + c])) p = r;
+        if (!(std::fabs(C[p * K + c]) > 0.0L)) throw std::runtime_error("singular split coupling");
+        if (p != c)
+            for (int q = 0; q < K; ++q) { std::swap(C[p * K + q], C[c * K + q]); std::swap(inv[p * K + q], inv[c * K + q]); }
+        const long double piv = C[c * K + c];
+        for (int q = 0; q < K; ++q) { C[c * K + q] /= piv; inv[c * K + q] /= piv; }
+        for (int r = 0; r < K; ++r) {
+            if (r == c) continue;
+            const long double f = C[r * K + c];
+            if (f == 0.0L) continue;
+            for (int q = 0; q < K; ++q) { C[r * K + q] -= f * C[c * K + q]; inv[r * K + q] -= f * inv[c * K + q]; }
+        }
+    }
+    for (int r = 0; r < K; ++r)
+        for (int c = 0; c < K; ++c) out[r * K + c] = static_cast<double>(inv[r * K + c] * d[c]);
+}
+
 }  // namespace
+
+int adi_split_row(int n) { return std::max(8, (n / 2 + 4) / 8 * 8); }
+
+bool adi_split_fits(int me_min, int ne_min) {
+    return me_min - adi_split_row(me_min) >= 3 && ne_min - adi_split_row(ne_min) >= 2 &&
+           adi_split_row(me_min) >= 8 && adi_split_row(ne_min) >= 8;
+}
 
 void mode_parameters(const DirOps& r, const DirOps& z, int w, double ka, double eps,
                      double zc, double zd, double* bounds4, int* J,
@@ -470,9 +549,18 @@ void mode_parameters(const DirOps& r, const DirOps& z, int w, double ka, double 
 }
 
 AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, double ka, double eps,
-                         bool flip) {
+                         bool flip, bool split) {
     AdiSetup s;
     s.kappa_alpha = ka; s.eps = eps; s.nw = g.nw;
+    s.split = split;
+    for (int par = 0; par < 2; ++par) {
+        s.rrows[par] = g.mp[par] + (split ? kRCouple : 0);
+        s.zrows[par] = g.np[par] + (split ? kZCouple : 0);
+        s.tr[par] = split ? adi_split_row(g.me[par]) : 0;
+        s.tz[par] = split ? adi_split_row(g.ne[par]) : 0;
+    }
+    if (split && !adi_split_fits(std::min(g.me[0], g.me[1]), std::min(g.ne[0], g.ne[1])))
+        throw std::logic_error("parity blocks too small for the split sweeps");
     double zc, zd;
     pencil_bounds_z(band_transpose(z.C02Q), band_transpose(z.D2Q), &zc, &zd);
 
@@ -483,7 +571,8 @@ AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, do
         if (flip) { Bp[par] = band_flip_transpose(Bp[par]); Dp[par] = band_flip_transpose(Dp[par]); }
     }
     // records per shift: both parity blocks, rows padded to a multiple of 8
-    const int me_sum = g.mp[0] + g.mp[1], ne_sum = g.np[0] + g.np[1];
+    // (plus the coupling rows of the split layout)
+    const int me_sum = s.rrows[0] + s.rrows[1], ne_sum = s.zrows[0] + s.zrows[1];
 
     s.J.resize(g.nw); s.bounds.resize(4 * g.nw);
     s.roff.resize(g.nw); s.zoff.resize(g.nw); s.soff.resize(g.nw);
@@ -498,7 +587,7 @@ AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, do
     }
     s.rtab.assign(rsz, 0.0); s.ztab.assign(zsz, 0.0); s.vmu.assign(ssz, 0.0);
 
-    std::vector<double> L, dinv, Us;
+    std::vector<double> L, dinv, Us, Up, dinvp, Ls;
     for (int w = 0; w < g.nw; ++w) {
         const Band Aw = radial_A(r, w);
         // pencil (A, C): Poisson (A_w, C~); heat (C~ - ka A_w, -ka C~)
@@ -521,15 +610,28 @@ AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, do
                 const Band Mv = band_axpby(vj, Cp[par], -1.0, Ap[par]);
                 if (Mu.lo != 2 || Mu.hi != 3) throw std::logic_error("unexpected r-band widths");
                 nopivot_lu(Mu, L, dinv, Us);
+                const int t_split = split ? s.tr[par] : Mu.rows;
+                if (split) nopivot_ul(Mu, Up, dinvp, Ls);
                 for (int i = 0; i < Mu.rows; ++i) {
                     double* rec = &s.rtab[base + static_cast<int64_t>(i) * kRRec];
                     for (int t = 0; t < 6; ++t) rec[t] = Mv.get(i, i - 2 + t);
-                    rec[6] = L[2 * i + 0];   // multiplier of g_{i-2}
-                    rec[7] = L[2 * i + 1];   // multiplier of g_{i-1}
-                    rec[8] = dinv[i];
-                    rec[9] = Us[3 * i + 0]; rec[10] = Us[3 * i + 1]; rec[11] = Us[3 * i + 2];
+                    if (i < t_split) {
+                        rec[6] = L[2 * i + 0];   // multiplier of g_{i-2}
+                        rec[7] = L[2 * i + 1];   // multiplier of g_{i-1}
+                        rec[8] = dinv[i];
+                        rec[9] = Us[3 * i + 0]; rec[10] = Us[3 * i + 1]; rec[11] = Us[3 * i + 2];
+                    } else {
+                        rec[6] = Up[3 * i + 0];  // multiplier of g'_{i+1}
+                        rec[7] = Up[3 * i + 1];  // multiplier of g'_{i+2}
+                        rec[8] = Up[3 * i + 2];  // multiplier of g'_{i+3}
+                        rec[9] = dinvp[i];
+                        rec[10] = Ls[2 * i + 0]; rec[11] = Ls[2 * i + 1];   // x_{i-1}, x_{i-2}
+                    }
                 }
-                base += static_cast<int64_t>(g.mp[par]) * kRRec;
+                if (split)
+                    split_coupling(2, 3, t_split, Us, dinv, Ls, dinvp,
+                                   &s.rtab[base + static_cast<int64_t>(g.mp[par]) * kRRec]);
+                base += static_cast<int64_t>(s.rrows[par]) * kRRec;
             }
             // z-direction records: solve x (v B + D) = z, then w = x (u' B + D)
             base = s.zoff[w] + static_cast<int64_t>(j) * ne_sum * kZRec;
@@ -539,15 +641,26 @@ AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, do
                 const Band Mn = band_axpby(un, Bp[par], 1.0, Dp[par]);
                 if (N.lo != 1 || N.hi != 2) throw std::logic_error("unexpected z-band widths");
                 nopivot_lu(N, L, dinv, Us);
+                const int t_split = split ? s.tz[par] : N.rows;
+                if (split) nopivot_ul(N, Up, dinvp, Ls);
                 for (int k = 0; k < N.rows; ++k) {
                     double* rec = &s.ztab[base + static_cast<int64_t>(k) * kZRec];
-                    rec[0] = L[k];
-                    rec[1] = dinv[k];
-                    rec[2] = Us[2 * k + 0]; rec[3] = Us[2 * k + 1];
+                    if (k < t_split) {
+                        rec[0] = L[k];
+                        rec[1] = dinv[k];
+                        rec[2] = Us[2 * k + 0]; rec[3] = Us[2 * k + 1];
+                    } else {
+                        rec[0] = Up[2 * k + 0]; rec[1] = Up[2 * k + 1];   // g'_{k+1}, g'_{k+2}
+                        rec[2] = dinvp[k];
+                        rec[3] = Ls[k];                                    // x_{k-1}
+                    }
                     if (j + 1 < J)
                         for (int t = 0; t < 4; ++t) rec[4 + t] = Mn.get(k - 1 + t, k);
                 }
-                base += static_cast<int64_t>(g.np[par]) * kZRec;
+                if (split)
+                    split_coupling(1, 2, t_split, Us, dinv, Ls, dinvp,
+                                   &s.ztab[base + static_cast<int64_t>(g.np[par]) * kZRec]);
+                base += static_cast<int64_t>(s.zrows[par]) * kZRec;
             }
         }
     }

@@ -71,6 +71,18 @@ DftTables build_dft_tables(int L);
 // Record layouts of the ADI coefficient tables (doubles per row).
 constexpr int kRRec = 12;   // r-pass: (vC - A) row[6], L[2], dinv, dinv*U[3]
 constexpr int kZRec = 8;    // z-pass: L, dinv, dinv*U[2], (u'B + D)^T row[4]
+// Split sweeps (two threads per line, see build_adi_setup): rows below the
+// split row t keep the LU records above; rows from t on hold UL records
+//   r-pass: (vC - A) row[6], U'[3], dinv', dinv' L'[2]   (L' at i-1, i-2)
+//   z-pass: U'[2], dinv', dinv' L'(k, k-1), (u'B + D)^T row[4]
+// and each parity block's records are followed by its coupling matrix
+// (r: 5 x 5 in kRCouple rows, z: 3 x 3 in kZCouple rows).
+constexpr int kRCouple = 3;
+constexpr int kZCouple = 2;
+// Split row of a line of n unknowns: a multiple of 8 near n / 2.
+int adi_split_row(int n);
+// True when every parity block is long enough for the split sweeps.
+bool adi_split_fits(int me_min, int ne_min);
 
 // Pencil + tolerance -> everything the ADI kernels read.
 struct AdiSetup {
@@ -82,6 +94,9 @@ struct AdiSetup {
     std::vector<double> rtab, ztab;     // coefficient records
     std::vector<double> vmu;            // per (w, j): v_j - u_j, offset soff[w]
     std::vector<int64_t> soff;
+    bool split = false;                 // split-sweep record layout
+    int rrows[2] = {0, 0}, zrows[2] = {0, 0};   // record rows per parity block and shift
+    int tr[2] = {0, 0}, tz[2] = {0, 0};         // split rows (split layout only)
     int J_max = 0, J_min = 0;
     double J_mean = 0.0;
 };
@@ -108,8 +123,12 @@ Geometry make_geometry(int m, int n, int p);
 // A^T Y B^T + C^T Y D^T = F written for Y~ = J Y J, F~ = J F J inside every
 // parity block, i.e. the pencil (J A^T J, J C^T J), (J B^T J, J D^T J); its
 // spectra, shifts and iteration counts are those of the untransposed pencil.
+// split: records for the two-thread sweeps.  A line of n unknowns is cut at
+// t = adi_split_row(n): rows [0, t) are eliminated downwards (LU), rows
+// [t, n) upwards (UL), the lo + hi unknowns around t follow from a small
+// coupling system, and each half then substitutes outwards from t.
 AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z,
-                         double kappa_alpha, double eps, bool flip = false);
+                         double kappa_alpha, double eps, bool flip = false, bool split = false);
 
 // Bounds/J/shifts of one wavenumber (shared by the setup and the host query).
 void mode_parameters(const DirOps& r, const DirOps& z, int w, double kappa_alpha,
