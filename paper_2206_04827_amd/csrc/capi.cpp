@@ -124,7 +124,7 @@ struct cyl_plan_s {
     Geometry geo;
     DirOps rops, zops;
     DftOwned dr, dz, dth;
-    DevMem pre_fr, post_fr, pre_ir, post_ir, pre_fz, post_fz, pre_iz, post_iz;
+    DevMem pre_fr, post_fr, pre_ir, post_ir, pre_fz, post_fz, pre_iz, post_iz, fold_r, fold_z;
     DevMem t_r2, t_a0, t_s10, t_c02, t_d2;
     RhsTables rhs{};
     DevMem plane_of, ztabA, atab_proj;
@@ -358,9 +358,9 @@ void transform_fwd(cyl_plan_t pl, const double* values, double2* coeffs) {
     const Geometry& g = pl->geo;
     hip_check(launch_theta_fwd(values, coeffs, g.m, g.n, g.p, pl->dth.view, pl->stream), "theta_fwd");
     hip_check(launch_dct(coeffs, coeffs, z_lines(g), g.n, false, pl->dz.view, pl->pre_fz.as<double>(),
-                         pl->post_fz.as<double>(), pl->stream), "dct_z_fwd");
+                         pl->post_fz.as<double>(), pl->fold_z.as<double2>(), pl->stream), "dct_z_fwd");
     hip_check(launch_dct(coeffs, coeffs, r_lines(g), g.m, true, pl->dr.view, pl->pre_fr.as<double>(),
-                         pl->post_fr.as<double>(), pl->stream), "dct_r_fwd");
+                         pl->post_fr.as<double>(), pl->fold_r.as<double2>(), pl->stream), "dct_r_fwd");
 }
 
 // coeffs may equal the plan's planesA (in place); coeffs is not modified otherwise.
@@ -369,9 +369,9 @@ void transform_inv(cyl_plan_t pl, const double2* coeffs, double* values) {
     const Geometry& g = pl->geo;
     double2* W = pl->planesA.as<double2>();
     hip_check(launch_dct(coeffs, W, r_lines(g), g.m, true, pl->dr.view, pl->pre_ir.as<double>(),
-                         pl->post_ir.as<double>(), pl->stream), "dct_r_inv");
+                         pl->post_ir.as<double>(), pl->fold_r.as<double2>(), pl->stream), "dct_r_inv");
     hip_check(launch_dct(W, W, z_lines(g), g.n, false, pl->dz.view, pl->pre_iz.as<double>(),
-                         pl->post_iz.as<double>(), pl->stream), "dct_z_inv");
+                         pl->post_iz.as<double>(), pl->fold_z.as<double2>(), pl->stream), "dct_z_inv");
     hip_check(launch_theta_inv(W, values, g.m, g.n, g.p, pl->dth.view, pl->stream), "theta_inv");
 }
 
@@ -470,8 +470,22 @@ void build_plan(cyl_plan_t pl) {
     pl->geo = make_geometry(m, n, p);
     pl->rops = build_dir_ops(m);
     pl->zops = build_dir_ops(n);
-    pl->dr.build(2 * (m - 1));
-    pl->dz.build(2 * (n - 1));
+    pl->dr.build(m - 1);
+    pl->dz.build(n - 1);
+    // fold table of the length-(M) DCT-I: (cos(pi j / M), sin(pi j / M)), j = 0..M
+    auto fold_tab = [](int len, DevMem& f) {
+        const int M = len - 1;
+        const long double pi = 3.141592653589793238462643383279502884L;
+        std::vector<double> v(2 * static_cast<size_t>(M + 1));
+        for (int j = 0; j <= M; ++j) {
+            const long double a = pi * static_cast<long double>(j) / static_cast<long double>(M);
+            v[2 * j] = static_cast<double>(std::cos(a));
+            v[2 * j + 1] = static_cast<double>(std::sin(a));
+        }
+        upload(f, v);
+    };
+    fold_tab(m, pl->fold_r);
+    fold_tab(n, pl->fold_z);
     pl->dth.build(p);
     // DCT pre/post factors: forward c_k = (-1)^k s_k / M * DCT-I(f)_k with
     // s_0 = s_M = 1/2; inverse f = DCT-I(g), g_k = (-1)^k c_k (halved inside).

@@ -43,10 +43,11 @@ hipError_t launch_theta_fwd(const double* values, double2* planes, int m, int n,
 hipError_t launch_theta_inv(const double2* planes, double* values, int m, int n, int p,
                             const DftDev& d, hipStream_t s);
 // DCT-I of every line: out_k = post[k] * sum_n pre[n] in_n * w_n cos(pi k n / M)
-// (w_n = 1 at both ends, 2 inside), M = mlen - 1.
+// (w_n = 1 at both ends, 2 inside), M = mlen - 1, through a length-M DFT
+// (d built for length M); fold[n] = (cos(pi n / M), sin(pi n / M)), n <= M.
 hipError_t launch_dct(const double2* in, double2* out, const LineSet& ls, int mlen,
                       bool contiguous_lines, const DftDev& d, const double* pre,
-                      const double* post, hipStream_t s);
+                      const double* post, const double2* fold, hipStream_t s);
 
 // ---- right-hand side (tau rows) and recombination ----
 struct RhsTables {

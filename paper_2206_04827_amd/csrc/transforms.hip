@@ -3,9 +3,9 @@
 // theta: a real DFT of length p along the slowest axis; two neighbouring
 //        r-lines are packed into one complex line (a + i b) and separated
 //        from the Hermitian symmetry of the result.
-// r, z : DCT-I of length M + 1 as the length-2M DFT of the even extension;
-//        complex lines carry the DCT of their real and imaginary parts at
-//        once.
+// r, z : DCT-I of length M + 1 through a length-M DFT of the folded line
+//        (see k_dct); complex lines carry the DCT of their real and
+//        imaginary parts at once.
 // Every DFT is a power-of-two Stockham FFT in LDS made of radix-16/8/4/2
 // passes whose butterflies run in registers; the twiddle table is staged in
 // LDS once per workgroup.  Lengths that are not powers of two go through
@@ -227,12 +227,23 @@ __device__ __forceinline__ void line_thread(int LPW, int TPL, int* li, int* t) {
     else           { *li = threadIdx.x / TPL; *t = threadIdx.x % TPL; }
 }
 
+// DCT-I of every line through a DFT of length M (not 2M).  With y = pre * in
+// (M + 1 points) and F_k = sum_n w_n y_n cos(pi k n / M), w = 1/2 at both ends:
+//   z_j = (y_j + y_{M-j}) / 2 - sin(pi j / M) (y_j - y_{M-j}),  j < M,
+//   C = DFT_M(z),
+//   F_{2k} = (C_k + C_{M-k}) / 2,
+//   F_{2k+1} = F_1 + sum_{k'=1..k} (i/2) (C_{k'} - C_{M-k'}),
+//   F_1 = sum_n w_n y_n cos(pi n / M),
+// which holds for complex y (real and imaginary parts at once).  The odd
+// outputs are a prefix sum: each thread scans a contiguous chunk, chunk
+// totals meet in LDS.  out_k = post_k * 2 F_k.
 // LDS: [twiddles: Nb][line 0: line_stride(Nb)][line 1] ...
 template <bool kLineFast>
 __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, LineSet ls,
                                               int mlen, DftDev d,
                                               const double* __restrict__ pre,
-                                              const double* __restrict__ post, int TPL, int LPW) {
+                                              const double* __restrict__ post,
+                                              const double2* __restrict__ fold, int TPL, int LPW) {
     extern __shared__ double2 lds[];
     double2* tws = lds;
     int li, t;
@@ -244,46 +255,101 @@ __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, Li
     if (valid) base = (line / ls.n_inner) * ls.outer + (line % ls.n_inner) * ls.inner;
     double2* buf = lds + d.Nb + li * line_stride(d.Nb);
     stage_twiddles(tws, d);
-    const int M = mlen - 1, L = 2 * M;
-    // the line has M + 1 <= Nb / 2 + 1 points: at most kPts / 2 + 1 per thread
-    constexpr int kIn = kPts / 2 + 1;
-    double2 v[kIn], ca[kIn], cb[kIn];
+    const int M = mlen - 1;
+    // M + 1 <= Nb + 1 points: at most kPts + 1 per thread
+    constexpr int kIn = kPts + 1;
+    double2 y[kIn], fc[kIn];
     double ps[kIn];
 #pragma unroll
     for (int c = 0; c < kIn; ++c) {
         const int s = t + c * TPL;
         const bool ok = s <= M;
-        v[c] = (ok && valid) ? in[base + s * ls.elem] : make_double2(0.0, 0.0);
+        y[c] = (ok && valid) ? in[base + s * ls.elem] : make_double2(0.0, 0.0);
         ps[c] = ok ? pre[s] : 0.0;
-        if (d.bluestein) {
-            ca[c] = ok ? d.chirp[s] : make_double2(0.0, 0.0);
-            cb[c] = (ok && s >= 1 && s < M) ? d.chirp[L - s] : make_double2(0.0, 0.0);
-        }
+        fc[c] = ok ? fold[s] : make_double2(0.0, 0.0);
     }
+    double2 f1 = make_double2(0.0, 0.0);
 #pragma unroll
     for (int c = 0; c < kIn; ++c) {
         const int s = t + c * TPL;
         if (s <= M) {
-            const double2 x = make_double2(v[c].x * ps[c], v[c].y * ps[c]);
-            buf[P(s)] = d.bluestein ? cmul(x, ca[c]) : x;
-            if (s >= 1 && s < M) buf[P(L - s)] = d.bluestein ? cmul(x, cb[c]) : x;
+            y[c] = make_double2(y[c].x * ps[c], y[c].y * ps[c]);
+            const double wc = ((s == 0 || s == M) ? 0.5 : 1.0) * fc[c].x;
+            f1 = make_double2(f1.x + wc * y[c].x, f1.y + wc * y[c].y);
+            buf[P(s)] = y[c];
         }
     }
-    for (int s = L + t; s < d.Nb; s += TPL) buf[P(s)] = make_double2(0.0, 0.0);
+    __syncthreads();
+    double2 z[kPts];
+#pragma unroll
+    for (int c = 0; c < kPts; ++c) {
+        const int j = t + c * TPL;
+        if (j < M) {
+            const double2 a = y[c], b = buf[P(M - j)];
+            const double sj = fc[c].y;
+            z[c] = make_double2(0.5 * (a.x + b.x) - sj * (a.x - b.x), 0.5 * (a.y + b.y) - sj * (a.y - b.y));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kPts; ++c) {
+        const int j = t + c * TPL;
+        if (j < M) buf[P(j)] = load_chirped(z[c], d, j);
+    }
+    for (int s = M + t; s < d.Nb; s += TPL) buf[P(s)] = make_double2(0.0, 0.0);
     __syncthreads();
     dft_lds(buf, d, tws, t, TPL);
+    // even outputs (strided) and odd increments (contiguous chunk per thread)
+    const int Ko = (M + 1) / 2;                 // odd outputs 1, 3, .., <= M
+    const int Q = (Ko + TPL - 1) / TPL;
+    double2 ev[kPts / 2 + 1], dk[kPts / 2 + 1];
+#pragma unroll
+    for (int c = 0; c < kPts / 2 + 1; ++c) {
+        const int k = t + c * TPL;
+        ev[c] = make_double2(0.0, 0.0);
+        if (2 * k <= M) {
+            const double2 a = buf[P(k)], b = buf[P(k == 0 ? 0 : M - k)];
+            ev[c] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y + b.y));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kPts / 2 + 1; ++q) {
+        const int k = t * Q + q;
+        dk[q] = make_double2(0.0, 0.0);
+        if (q < Q && k >= 1 && k < Ko) {
+            const double2 a = buf[P(k)], b = buf[P(M - k)];
+            dk[q] = make_double2(-0.5 * (a.y - b.y), 0.5 * (a.x - b.x));      // (i/2)(C_k - C_{M-k})
+        }
+    }
+#pragma unroll
+    for (int q = 1; q < kPts / 2 + 1; ++q) dk[q] = make_double2(dk[q].x + dk[q - 1].x, dk[q].y + dk[q - 1].y);
+    __syncthreads();
+    const double2 tot = dk[kPts / 2];
+    buf[P(t)] = tot;
+    buf[P(TPL + t)] = f1;
+    __syncthreads();
+    double2 off = make_double2(0.0, 0.0), F1 = make_double2(0.0, 0.0);
+    for (int u = 0; u < TPL; ++u) {
+        const double2 a = buf[P(u)], b = buf[P(TPL + u)];
+        if (u < t) off = make_double2(off.x + a.x, off.y + a.y);
+        F1 = make_double2(F1.x + b.x, F1.y + b.y);
+    }
     if (valid) {
 #pragma unroll
-        for (int c = 0; c < kIn; ++c) {
+        for (int c = 0; c < kPts / 2 + 1; ++c) {
             const int k = t + c * TPL;
-            ps[c] = k <= M ? post[k] : 0.0;
+            if (2 * k <= M) {
+                const double sc = 2.0 * post[2 * k];
+                out[base + (2 * k) * ls.elem] = make_double2(sc * ev[c].x, sc * ev[c].y);
+            }
         }
 #pragma unroll
-        for (int c = 0; c < kIn; ++c) {
-            const int k = t + c * TPL;
-            if (k <= M) {
-                const double2 X = buf[P(k)];
-                out[base + k * ls.elem] = make_double2(X.x * ps[c], X.y * ps[c]);
+        for (int q = 0; q < kPts / 2 + 1; ++q) {
+            const int k = t * Q + q;
+            if (q < Q && k < Ko) {
+                const double sc = 2.0 * post[2 * k + 1];
+                out[base + (2 * k + 1) * ls.elem] =
+                    make_double2(sc * (F1.x + off.x + dk[q].x), sc * (F1.y + off.y + dk[q].y));
             }
         }
     }
@@ -427,7 +493,7 @@ hipError_t launch_theta_inv(const double2* planes, double* values, int m, int n,
 
 hipError_t launch_dct(const double2* in, double2* out, const LineSet& ls, int mlen,
                       bool contiguous_lines, const DftDev& d, const double* pre,
-                      const double* post, hipStream_t s) {
+                      const double* post, const double2* fold, hipStream_t s) {
     int TPL, LPW, threads;
     size_t lds;
     line_config(d.Nb, !contiguous_lines, &TPL, &LPW, &threads, &lds);
@@ -435,10 +501,10 @@ hipError_t launch_dct(const double2* in, double2* out, const LineSet& ls, int ml
     const unsigned grid = static_cast<unsigned>((lines + LPW - 1) / LPW);
     if (contiguous_lines) {
         raise_lds(k_dct<false>, lds);
-        hipLaunchKernelGGL(k_dct<false>, dim3(grid), dim3(threads), lds, s, in, out, ls, mlen, d, pre, post, TPL, LPW);
+        hipLaunchKernelGGL(k_dct<false>, dim3(grid), dim3(threads), lds, s, in, out, ls, mlen, d, pre, post, fold, TPL, LPW);
     } else {
         raise_lds(k_dct<true>, lds);
-        hipLaunchKernelGGL(k_dct<true>, dim3(grid), dim3(threads), lds, s, in, out, ls, mlen, d, pre, post, TPL, LPW);
+        hipLaunchKernelGGL(k_dct<true>, dim3(grid), dim3(threads), lds, s, in, out, ls, mlen, d, pre, post, fold, TPL, LPW);
     }
     return hipGetLastError();
 }
