@@ -878,82 +878,125 @@ void k_adi_global(const BlockDesc* __restrict__ blocks, const double* __restrict
 // tau right-hand side (eq. HelmholtzMatEqn, right side, with r^2 weighting):
 //   E = sF [R2 (F + cL L) C02^T]_tau + sL [A_w L C02^T + R2 L D2^T]_tau
 // written into the parity blocks (E-layout) of each real mode plane.
+// One workgroup per (w, 64 tau rows, 16 tau columns): the input tile
+// (rows i0-2 .. i0+69, columns k0 .. k0+19, both real planes of w as one
+// complex value) is staged in LDS with reads along r; the z taps (C02, 3)
+// and then the r taps (R2, 5) are applied separably; each store writes 32
+// consecutive rows of one parity block's column.
 // ---------------------------------------------------------------------------
+constexpr int kRI = 64, kRK = 16;
+constexpr int kRA = kRI + 8, kRL = kRK + 4;
+
+template <bool kLift>
 __global__ __launch_bounds__(256) void k_rhs(const double2* __restrict__ F,
                                              const double2* __restrict__ L, double sF, double cL,
                                              double sL, double* __restrict__ E,
-                                             const BlockDesc* __restrict__ blocks, int m, int n,
+                                             const BlockDesc* __restrict__ blocks,
+                                             const int* __restrict__ plane_of, int m, int n,
                                              RhsTables t) {
-    const int plane = blockIdx.y;
-    const int mi = m - 2, ni = n - 2;
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= static_cast<int64_t>(mi) * ni) return;
-    const int i = static_cast<int>(e % mi), k = static_cast<int>(e / mi);
-    const BlockDesc b0 = blocks[4 * plane];
-    const int w = b0.w, part = b0.part;
+    extern __shared__ double2 rsm[];
+    double2* fs = rsm;                  // [kRL][kRA]  F + cL L
+    double2* gs = fs + kRL * kRA;       // [kRK][kRA]  (F + cL L) C02^T
+    double2* lt = gs + kRK * kRA;       // lift only: [kRL][kRA] L
+    double2* gl = lt + kRL * kRA;       //            [kRK][kRA] L C02^T
+    double2* ld = gl + kRK * kRA;       //            [kRK][kRA] L D2^T
+    const int w = blockIdx.z, i0 = blockIdx.x * kRI, k0 = blockIdx.y * kRK;
+    const int mi = m - 2, ni = n - 2, tid = threadIdx.x;
     const double2* Fw = F + static_cast<int64_t>(w) * n * m;
-    const double2* Lw = L ? L + static_cast<int64_t>(w) * n * m : nullptr;
-    auto comp = [part](double2 v) { return part ? v.y : v.x; };
-    const double* c02 = t.c02 + 3 * k;
-    const double* r2 = t.r2 + 5 * i;
-    double acc = 0.0;
-#pragma unroll
-    for (int ta = 0; ta < 5; ++ta) {
-        const int a = i - 2 + 2 * ta;
-        if (a < 0 || a >= m || r2[ta] == 0.0) continue;
-        double fz = 0.0;
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            const int l = k + 2 * s;
-            if (l >= n) continue;
-            const int64_t o = static_cast<int64_t>(l) * m + a;
-            double fv = comp(Fw[o]);
-            if (Lw != nullptr && cL != 0.0) fv += cL * comp(Lw[o]);
-            fz += c02[s] * fv;
+    const double2* Lw = kLift ? L + static_cast<int64_t>(w) * n * m : nullptr;
+    for (int idx = tid; idx < kRL * kRA; idx += blockDim.x) {
+        const int ll = idx / kRA, al = idx - ll * kRA;
+        const int a = i0 - 2 + al, l = k0 + ll;
+        double2 f = make_double2(0.0, 0.0), lv = make_double2(0.0, 0.0);
+        if (a >= 0 && a < m && l < n) {
+            f = Fw[static_cast<int64_t>(l) * m + a];
+            if (kLift) lv = Lw[static_cast<int64_t>(l) * m + a];
         }
-        acc += r2[ta] * fz;
+        if (kLift) {
+            lt[idx] = lv;
+            f = make_double2(f.x + cL * lv.x, f.y + cL * lv.y);
+        }
+        fs[idx] = f;
     }
-    acc *= sF;
-    if (Lw != nullptr && sL != 0.0) {
-        const double ww = static_cast<double>(w) * w;
-        const double* a0 = t.a0 + 4 * i;
-        const double* s10 = t.s10 + 4 * i;
-        double lacc = 0.0;
-#pragma unroll
-        for (int ta = 0; ta < 4; ++ta) {
-            const int a = i - 2 + 2 * ta;
-            const double aw = a0[ta] - ww * s10[ta];
-            if (a < 0 || a >= m || aw == 0.0) continue;
-            double lc = 0.0;
+    __syncthreads();
+    for (int idx = tid; idx < kRK * kRA; idx += blockDim.x) {
+        const int kl = idx / kRA, al = idx - kl * kRA;
+        const int k = k0 + kl;
+        double2 g = make_double2(0.0, 0.0), gL = g, dL = g;
+        if (k < ni) {
+            const double* c = t.c02 + 3 * k;
 #pragma unroll
             for (int s = 0; s < 3; ++s) {
-                const int l = k + 2 * s;
-                if (l < n) lc += c02[s] * comp(Lw[static_cast<int64_t>(l) * m + a]);
+                const double2 v = fs[(kl + 2 * s) * kRA + al];
+                g = make_double2(g.x + c[s] * v.x, g.y + c[s] * v.y);
+                if (kLift) {
+                    const double2 u = lt[(kl + 2 * s) * kRA + al];
+                    gL = make_double2(gL.x + c[s] * u.x, gL.y + c[s] * u.y);
+                }
             }
-            lacc += aw * lc;
+            if (kLift) {
+                const double d = t.d2[k];
+                const double2 u = lt[(kl + 2) * kRA + al];
+                dL = make_double2(d * u.x, d * u.y);
+            }
         }
-        const double d2 = t.d2[k];
+        gs[idx] = g;
+        if (kLift) { gl[idx] = gL; ld[idx] = dL; }
+    }
+    __syncthreads();
+    const int il = tid & 31, rest = tid >> 5;
+    const int p0 = plane_of[2 * w], p1 = plane_of[2 * w + 1];
+    const double ww = static_cast<double>(w) * w;
+    for (int c = 0; c < (2 * kRK) / 8; ++c) {
+        const int combo = rest + 8 * c;
+        const int pr = combo & 1, kl = combo >> 1;
+        const int i = i0 + 2 * il + pr, k = k0 + kl;
+        if (i >= mi || k >= ni) continue;
+        const double* r2 = t.r2 + 5 * i;
+        const double2* gk = gs + kl * kRA + (i - i0);
+        double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
         for (int ta = 0; ta < 5; ++ta) {
-            const int a = i - 2 + 2 * ta;
-            if (a < 0 || a >= m || r2[ta] == 0.0) continue;
-            lacc += r2[ta] * d2 * comp(Lw[static_cast<int64_t>(k + 2) * m + a]);
+            const double2 v = gk[2 * ta];
+            acc = make_double2(acc.x + r2[ta] * v.x, acc.y + r2[ta] * v.y);
         }
-        acc += sL * lacc;
+        acc = make_double2(sF * acc.x, sF * acc.y);
+        if (kLift) {
+            const double* a0 = t.a0 + 4 * i;
+            const double* s10 = t.s10 + 4 * i;
+            const double2* glk = gl + kl * kRA + (i - i0);
+            const double2* ldk = ld + kl * kRA + (i - i0);
+            double2 la = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int ta = 0; ta < 4; ++ta) {
+                const double aw = a0[ta] - ww * s10[ta];
+                const double2 v = glk[2 * ta];
+                la = make_double2(la.x + aw * v.x, la.y + aw * v.y);
+            }
+#pragma unroll
+            for (int ta = 0; ta < 5; ++ta) {
+                const double2 v = ldk[2 * ta];
+                la = make_double2(la.x + r2[ta] * v.x, la.y + r2[ta] * v.y);
+            }
+            acc = make_double2(acc.x + sL * la.x, acc.y + sL * la.y);
+        }
+        const int bsel = 2 * pr + (k & 1);
+        const BlockDesc& b0 = blocks[4 * p0 + bsel];
+        const int64_t o = static_cast<int64_t>(k >> 1) * b0.mp + (i >> 1);
+        E[b0.eoff + o] = acc.x;
+        if (p1 >= 0) E[blocks[4 * p1 + bsel].eoff + o] = acc.y;
     }
-    const BlockDesc bd = blocks[4 * plane + 2 * (i & 1) + (k & 1)];
-    E[bd.eoff + static_cast<int64_t>(k >> 1) * bd.mp + (i >> 1)] = acc;
 }
 
 // ---------------------------------------------------------------------------
-// recombination U = Q_m Xt Q_n^T (+ L) into complex coefficient planes.
+// recombination U = Q_m Xt Q_n^T (+ L) into complex coefficient planes:
+//   U[a, l] = Xt[a-2, l-2] - Xt[a-2, l] - Xt[a, l-2] + Xt[a, l].
+// One workgroup per (w, 64 r-points, 32 z-points): the Xt tile of both real
+// planes (rows a0-2 .. a0+63, columns l0-2 .. l0+31) is read along z from the
+// row-major parity blocks into LDS, and the planes are written along r.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double xt_at(const double* X, const BlockDesc* blocks, int plane,
-                                        int i, int k, int mi, int ni) {
-    if (plane < 0 || i < 0 || k < 0 || i >= mi || k >= ni) return 0.0;
-    const BlockDesc& bd = blocks[4 * plane + 2 * (i & 1) + (k & 1)];
-    return X[bd.xoff + static_cast<int64_t>(i >> 1) * bd.ne + (k >> 1)];
-}
+constexpr int kCA = 64, kCL = 32;
+constexpr int kCS = kCA + 3;          // LDS row length (odd: conflict-free both ways)
 
 __global__ __launch_bounds__(256) void k_recombine(const double* __restrict__ X,
                                                    const double2* __restrict__ L,
@@ -961,35 +1004,58 @@ __global__ __launch_bounds__(256) void k_recombine(const double* __restrict__ X,
                                                    const int* __restrict__ plane_of,
                                                    const BlockDesc* __restrict__ blocks, int m,
                                                    int n) {
-    const int w = blockIdx.y;
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= static_cast<int64_t>(m) * n) return;
-    const int a = static_cast<int>(e % m), l = static_cast<int>(e / m);
-    const int mi = m - 2, ni = n - 2;
-    double v[2];
+    __shared__ double2 xs[(kCL + 2) * kCS];
+    const int w = blockIdx.z, a0 = blockIdx.x * kCA, l0 = blockIdx.y * kCL;
+    const int mi = m - 2, ni = n - 2, tid = threadIdx.x;
+    const int p0 = plane_of[2 * w], p1 = plane_of[2 * w + 1];
+    int64_t x0[4], x1[4];
+    int neb[4];
 #pragma unroll
-    for (int part = 0; part < 2; ++part) {
-        const int pl = plane_of[2 * w + part];
-        v[part] = xt_at(X, blocks, pl, a - 2, l - 2, mi, ni) - xt_at(X, blocks, pl, a - 2, l, mi, ni) -
-                  xt_at(X, blocks, pl, a, l - 2, mi, ni) + xt_at(X, blocks, pl, a, l, mi, ni);
+    for (int b = 0; b < 4; ++b) {
+        x0[b] = blocks[4 * p0 + b].xoff;
+        neb[b] = blocks[4 * p0 + b].ne;
+        x1[b] = p1 >= 0 ? blocks[4 * p1 + b].xoff : 0;
     }
-    const int64_t off = (static_cast<int64_t>(w) * n + l) * m + a;
-    double2 out = make_double2(v[0], v[1]);
-    if (L != nullptr) {
-        const double2 lv = L[off];
-        out.x += lv.x;
-        if (plane_of[2 * w + 1] >= 0) out.y += lv.y;
+    for (int idx = tid; idx < (kCA + 2) * (kCL + 2); idx += blockDim.x) {
+        const int il = idx / (kCL + 2), kl = idx - il * (kCL + 2);
+        const int i = a0 - 2 + il, k = l0 - 2 + kl;
+        double2 v = make_double2(0.0, 0.0);
+        if (i >= 0 && i < mi && k >= 0 && k < ni) {
+            const int b = 2 * (i & 1) + (k & 1);
+            const int64_t o = static_cast<int64_t>(i >> 1) * neb[b] + (k >> 1);
+            v.x = X[x0[b] + o];
+            if (p1 >= 0) v.y = X[x1[b] + o];
+        }
+        xs[kl * kCS + il] = v;
     }
-    planes[off] = out;
+    __syncthreads();
+    for (int idx = tid; idx < kCA * kCL; idx += blockDim.x) {
+        const int al = idx % kCA, ll = idx / kCA;
+        const int a = a0 + al, l = l0 + ll;
+        if (a >= m || l >= n) continue;
+        const double2 p = xs[ll * kCS + al], q = xs[(ll + 2) * kCS + al];
+        const double2 r = xs[ll * kCS + al + 2], s = xs[(ll + 2) * kCS + al + 2];
+        double2 u = make_double2(p.x - q.x - r.x + s.x, p.y - q.y - r.y + s.y);
+        const int64_t off = (static_cast<int64_t>(w) * n + l) * m + a;
+        if (L != nullptr) {
+            const double2 lv = L[off];
+            u.x += lv.x;
+            if (p1 >= 0) u.y += lv.y;
+        }
+        planes[off] = u;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // out = sE E - sAB (A X B) - sCD (C X D), blockwise; X in X-layout, E and out
 // in E-layout.  One workgroup per 32 x 32 output tile; the X tile with its
-// halo (rows -2..+3, columns -1..+2) is staged in LDS.
+// halo (rows -2..+3, columns -1..+2) and the tile's column records are
+// staged in LDS; each thread keeps its row's records in registers and
+// produces four outputs of that row.
 // ---------------------------------------------------------------------------
 constexpr int kTile = 32;
 constexpr int kTR = kTile + 5, kTC = kTile + 3;
+constexpr int kTS = kTC + 2;          // odd LDS row length (conflict-free row reads)
 
 __global__ __launch_bounds__(256) void k_apply(const BlockDesc* __restrict__ blocks,
                                                const double* __restrict__ E, double sE,
@@ -997,38 +1063,49 @@ __global__ __launch_bounds__(256) void k_apply(const BlockDesc* __restrict__ blo
                                                double sCD, double* __restrict__ out,
                                                const double* __restrict__ atab, int64_t a_wstride,
                                                int me0, const double* __restrict__ ztabA, int ne0) {
-    __shared__ double xs[kTR][kTC + 1];
+    __shared__ double xs[kTR * kTS];
+    __shared__ double zs[kTile * 8];
     const BlockDesc bd = blocks[blockIdx.z];
     const int me = bd.me, ne = bd.ne;
     const int i0 = blockIdx.x * kTile, k0 = blockIdx.y * kTile;
     if (i0 >= me || k0 >= ne) return;
+    const int tid = threadIdx.x;
     const double* Xb = X + bd.xoff;
-    for (int idx = threadIdx.x; idx < kTR * kTC; idx += blockDim.x) {
+    for (int idx = tid; idx < kTR * kTC; idx += blockDim.x) {
         const int r = idx / kTC, c = idx - r * kTC;
         const int a = i0 - 2 + r, l = k0 - 1 + c;
-        xs[r][c] = (a >= 0 && a < me && l >= 0 && l < ne) ? Xb[static_cast<int64_t>(a) * ne + l] : 0.0;
+        xs[r * kTS + c] = (a >= 0 && a < me && l >= 0 && l < ne) ? Xb[static_cast<int64_t>(a) * ne + l] : 0.0;
+    }
+    const double* zcol = ztabA + (bd.pz ? ne0 * 8 : 0);
+    for (int idx = tid; idx < kTile * 8; idx += blockDim.x) {
+        const int k = k0 + (idx >> 3);
+        zs[idx] = k < ne ? zcol[k0 * 8 + idx] : 0.0;
     }
     __syncthreads();
-    const double* arow = atab + bd.w * a_wstride + (bd.pr ? me0 * 12 : 0);
-    const double* zcol = ztabA + (bd.pz ? ne0 * 8 : 0);
-    for (int idx = threadIdx.x; idx < kTile * kTile; idx += blockDim.x) {
-        const int di = idx % kTile, dk = idx / kTile;
-        const int i = i0 + di, k = k0 + dk;
-        if (i >= me || k >= ne) continue;
-        const double* ar = arow + i * 12;
-        const double* zc = zcol + k * 8;
+    const int di = tid & 31, kq = tid >> 5;
+    const int i = i0 + di;
+    if (i >= me) return;
+    const double* ar = atab + bd.w * a_wstride + (bd.pr ? me0 * 12 : 0) + i * 12;
+    double a[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) a[q] = ar[q];
+#pragma unroll
+    for (int c = 0; c < kTile / 8; ++c) {
+        const int dk = kq + 8 * c, k = k0 + dk;
+        if (k >= ne) continue;
+        const double* zc = zs + dk * 8;
         double sab = 0.0, scd = 0.0;
 #pragma unroll
         for (int da = 0; da < 6; ++da) {
             double xb = 0.0, xd = 0.0;
 #pragma unroll
             for (int dl = 0; dl < 4; ++dl) {
-                const double x = xs[di + da][dk + dl];
+                const double x = xs[(di + da) * kTS + dk + dl];
                 xb += x * zc[dl];
                 xd += x * zc[4 + dl];
             }
-            sab += ar[da] * xb;
-            scd += ar[6 + da] * xd;
+            sab += a[da] * xb;
+            scd += a[6 + da] * xd;
         }
         const int64_t o = bd.eoff + static_cast<int64_t>(k) * bd.mp + i;
         const double ev = (sE != 0.0) ? sE * E[o] : 0.0;
@@ -1161,11 +1238,27 @@ hipError_t adi_set_lds_limit(int np0, size_t bytes) {
 }
 
 hipError_t launch_rhs3(const double2* F, const double2* L, double sF, double cL, double sL,
-                       double* E, const BlockDesc* blocks, int nplanes, int m, int n,
+                       double* E, const BlockDesc* blocks, const int* plane_of, int nw, int m, int n,
                        const RhsTables& t, hipStream_t s) {
-    const int64_t cnt = static_cast<int64_t>(m - 2) * (n - 2);
-    const dim3 grid(static_cast<unsigned>((cnt + 255) / 256), nplanes);
-    hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, s, F, L, sF, cL, sL, E, blocks, m, n, t);
+    const dim3 grid(static_cast<unsigned>((m - 2 + kRI - 1) / kRI),
+                    static_cast<unsigned>((n - 2 + kRK - 1) / kRK), static_cast<unsigned>(nw));
+    if (L != nullptr) {
+        const size_t lds = static_cast<size_t>(2 * kRL + 3 * kRK) * kRA * sizeof(double2);
+        static bool raised = false;
+        if (!raised) {
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rhs<true>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     static_cast<int>(lds));
+            if (e != hipSuccess) return e;
+            raised = true;
+        }
+        hipLaunchKernelGGL(k_rhs<true>, grid, dim3(256), lds, s, F, L, sF, cL, sL, E, blocks, plane_of,
+                           m, n, t);
+    } else {
+        const size_t lds = static_cast<size_t>(kRL + kRK) * kRA * sizeof(double2);
+        hipLaunchKernelGGL(k_rhs<false>, grid, dim3(256), lds, s, F, L, sF, cL, sL, E, blocks, plane_of,
+                           m, n, t);
+    }
     return hipGetLastError();
 }
 
@@ -1173,8 +1266,8 @@ hipError_t launch_recombine(const double* X, const double2* L, double2* planes,
                             const int* plane_of, const BlockDesc* blocks, int nw, int m, int n,
                             int p, hipStream_t s) {
     (void)p;
-    const int64_t cnt = static_cast<int64_t>(m) * n;
-    const dim3 grid(static_cast<unsigned>((cnt + 255) / 256), nw);
+    const dim3 grid(static_cast<unsigned>((m + kCA - 1) / kCA), static_cast<unsigned>((n + kCL - 1) / kCL),
+                    static_cast<unsigned>(nw));
     hipLaunchKernelGGL(k_recombine, grid, dim3(256), 0, s, X, L, planes, plane_of, blocks, m, n);
     return hipGetLastError();
 }

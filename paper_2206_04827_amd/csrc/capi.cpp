@@ -691,7 +691,7 @@ int cyl_poisson_solve(cyl_plan_t plan, int space, const double* f, const double*
         {
             Scope sc(pl, PH_RHS);
             hip_check(launch_rhs3(F, Lc, 1.0, 0.0, -1.0, pl->E.as<double>(), s->blocks.as<BlockDesc>(),
-                                  g.nplanes, g.m, g.n, pl->rhs, pl->stream), "rhs");
+                                  pl->plane_of.as<int>(), g.nw, g.m, g.n, pl->rhs, pl->stream), "rhs");
         }
         adi_solve(pl, s, pl->E.as<double>(), pl->X.as<double>());
         if (info) check_residual(pl, s, pl->E.as<double>(), pl->X.as<double>(), adi_tol, info);
@@ -759,8 +759,8 @@ int cyl_heat_create(cyl_heat_t* h, cyl_plan_t plan, double alpha, double dt, int
                 C = reinterpret_cast<const double2*>(history[i]);
             }
             Scope sc(pl, PH_RHS);
-            hip_check(launch_rhs3(C, Lc, 1.0, -1.0, 0.0, H->P[i].as<double>(), blocks, geo.nplanes, geo.m,
-                                  geo.n, pl->rhs, pl->stream), "history rhs");
+            hip_check(launch_rhs3(C, Lc, 1.0, -1.0, 0.0, H->P[i].as<double>(), blocks, pl->plane_of.as<int>(),
+                                  geo.nw, geo.m, geo.n, pl->rhs, pl->stream), "history rhs");
         }
         // constant part: kappa [R2 G C02^T]_tau + kappa alpha [r^2 nabla^2 L]_tau
         const double2* G;
@@ -772,8 +772,9 @@ int cyl_heat_create(cyl_heat_t* h, cyl_plan_t plan, double alpha, double dt, int
         }
         {
             Scope sc(pl, PH_RHS);
-            hip_check(launch_rhs3(G, Lc, H->kappa, 0.0, ka, H->Econst.as<double>(), blocks, geo.nplanes,
-                                  geo.m, geo.n, pl->rhs, pl->stream), "forcing rhs");
+            hip_check(launch_rhs3(G, Lc, H->kappa, 0.0, ka, H->Econst.as<double>(), blocks,
+                                  pl->plane_of.as<int>(), geo.nw, geo.m, geo.n, pl->rhs, pl->stream),
+                      "forcing rhs");
         }
         H->head = 0;
         *h = H.release();
@@ -964,8 +965,8 @@ int cyl_heat_grad_forward(cyl_heat_grad_t a) {
         {
             Scope sc(pl, PH_RHS);
             hip_check(launch_rhs3(h->T0.as<double2>(), nullptr, 1.0, 0.0, 0.0, ckpt_slot(a, 0),
-                                  h->setup->blocks.as<BlockDesc>(), g.nplanes, g.m, g.n, pl->rhs,
-                                  pl->stream), "initial projection");
+                                  h->setup->blocks.as<BlockDesc>(), pl->plane_of.as<int>(), g.nw, g.m, g.n,
+                                  pl->rhs, pl->stream), "initial projection");
         }
         const double* cur = ckpt_slot(a, 0);
         for (int k = 1; k <= N; ++k) {

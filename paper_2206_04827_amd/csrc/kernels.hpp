@@ -58,8 +58,9 @@ struct RhsTables {
     const double* d2;    // (n-2)     : D2 row k at k+2
 };
 // E = sF [R2 (F + cL L) C02^T]_tau + sL [A_w L C02^T + R2 L D2^T]_tau (L may be NULL)
+// plane_of[2 w + part]: real plane of (w, part), -1 if none; nw = floor(p/2) + 1.
 hipError_t launch_rhs3(const double2* F, const double2* L, double sF, double cL, double sL,
-                       double* E, const BlockDesc* blocks, int nplanes, int m, int n,
+                       double* E, const BlockDesc* blocks, const int* plane_of, int nw, int m, int n,
                        const RhsTables& t, hipStream_t s);
 hipError_t launch_recombine(const double* X, const double2* L, double2* planes,
                             const int* block_of_plane, const BlockDesc* blocks, int nw,
