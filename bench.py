@@ -37,8 +37,8 @@ ADI_FLOPS_PER_UNKNOWN_ITER = 38.0
 # HBM bytes per ADI launch at 256^3 from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # (scaled by a 512 MiB copy: fetch x2.0, write x1.0), valid for the ADI source
 # whose SHA-256 starts with ADI_TRAFFIC_SHA; reported as null otherwise.
-ADI_TRAFFIC_BYTES_256 = 2.495e9
-ADI_TRAFFIC_SHA = "9e8850efd60acb30"
+ADI_TRAFFIC_BYTES_256 = 2.559e9
+ADI_TRAFFIC_SHA = "0ffc5851bedef06e"
 
 
 def parse():
@@ -201,7 +201,7 @@ def main():
     traffic = ADI_TRAFFIC_BYTES_256 if (sha == ADI_TRAFFIC_SHA and m == 256 and passes == 2) else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": "k_adi_lds (one ADI pass over all parity blocks)",
+                "kernel": "k_adi_split (one ADI pass over all parity blocks)",
                 "avg_launch_ms": round(adi_ms, 4), "launches": n_adi}
     phases = {k[3:]: round(prof[k] / args.steps, 4) for k in prof if k.startswith("ms_")}
 
