@@ -28,7 +28,7 @@ def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):   # host-only translation units
-        cmd = [HIPCC, "-x", "c++", "-O3", "-std=c++17", "-fPIC", "-Wall",
+        cmd = [HIPCC, "-x", "c++", "-O3", "-std=c++17", "-fPIC", "-Wall", "-pthread",
                "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROCM, "include"),
                "-D__HIP_PLATFORM_AMD__", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -48,7 +48,7 @@ def build(verbose=False):
             raise RuntimeError("compilation of %s failed" % src)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", "-pthread", "--offload-arch=gfx950", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if verbose or r.returncode != 0:
         print(" ".join(cmd))

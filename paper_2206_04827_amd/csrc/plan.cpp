@@ -4,10 +4,13 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
+#include <exception>
 #include <stdexcept>
 #include <string>
+#include <thread>
 
 namespace cyl {
 
@@ -527,6 +530,34 @@ void split_coupling(int lo, int hi, int t, const std::vector<double>& Us, const 
 
 }  // namespace
 
+// Run f(i) for i in [0, n) on up to 16 host threads; the first exception
+// thrown by any f(i) is rethrown in the caller.
+template <typename F>
+void parallel_for(int n, F&& f) {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int T = std::min(n, static_cast<int>(std::min(hw, 16u)));
+    if (T <= 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::vector<std::exception_ptr> errs(T);
+    std::vector<std::thread> pool;
+    pool.reserve(T);
+    for (int t = 0; t < T; ++t)
+        pool.emplace_back([&, t] {
+            try {
+                for (int i = next++; i < n; i = next++) f(i);
+            } catch (...) {
+                errs[t] = std::current_exception();
+                next = n;
+            }
+        });
+    for (auto& th : pool) th.join();
+    for (auto& e : errs)
+        if (e) std::rethrow_exception(e);
+}
+
 int adi_split_row(int n) { return std::max(8, (n / 2 + 4) / 8 * 8); }
 
 bool adi_split_fits(int me_min, int ne_min) {
@@ -578,8 +609,10 @@ AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, do
     s.roff.resize(g.nw); s.zoff.resize(g.nw); s.soff.resize(g.nw);
     int64_t rsz = 0, zsz = 0, ssz = 0;
     std::vector<std::vector<double>> U(g.nw), V(g.nw);
-    for (int w = 0; w < g.nw; ++w) {
+    parallel_for(g.nw, [&](int w) {
         mode_parameters(r, z, w, ka, eps, zc, zd, &s.bounds[4 * w], &s.J[w], &U[w], &V[w]);
+    });
+    for (int w = 0; w < g.nw; ++w) {
         s.roff[w] = rsz; s.zoff[w] = zsz; s.soff[w] = ssz;
         rsz += static_cast<int64_t>(s.J[w]) * me_sum * kRRec;
         zsz += static_cast<int64_t>(s.J[w]) * ne_sum * kZRec;
@@ -587,8 +620,8 @@ AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, do
     }
     s.rtab.assign(rsz, 0.0); s.ztab.assign(zsz, 0.0); s.vmu.assign(ssz, 0.0);
 
-    std::vector<double> L, dinv, Us, Up, dinvp, Ls;
-    for (int w = 0; w < g.nw; ++w) {
+    parallel_for(g.nw, [&](int w) {
+        std::vector<double> L, dinv, Us, Up, dinvp, Ls;
         const Band Aw = radial_A(r, w);
         // pencil (A, C): Poisson (A_w, C~); heat (C~ - ka A_w, -ka C~)
         const Band A = ka > 0.0 ? band_axpby(1.0, r.R2Q, -ka, Aw) : Aw;
@@ -663,7 +696,7 @@ AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, do
                 base += static_cast<int64_t>(s.zrows[par]) * kZRec;
             }
         }
-    }
+    });
     s.J_max = *std::max_element(s.J.begin(), s.J.end());
     s.J_min = *std::min_element(s.J.begin(), s.J.end());
     double sum = 0.0;
