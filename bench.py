@@ -14,7 +14,11 @@ Prints one JSON line.  Besides the headline value it carries:
   heat_fwd_adjoint_192
                 forward + adjoint BDF1 heat steps per second at 192^3: 200
                 steps, alpha = 1, dt = 1e-3, checkpoint every 20 steps, loss
-                |T_N - T_target|^2, gradients for T0, g and alpha.
+                |T_N - T_target|^2, gradients for T0, g and alpha;
+  batched_64    64 independent BDF1 heat problems of uneven sizes (n_r = n_z
+                in 48..384, n_theta in 32..256, alpha in [0.1, 2]), 50 steps:
+                batched launches with a replayed step graph against stepping
+                each problem on its own.
 """
 
 import argparse
@@ -52,6 +56,9 @@ def parse():
     ap.add_argument("--no-heat", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-reps", type=int, default=2)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--cpu-modes", type=int, default=16,
                     help="wavenumbers the CPU oracle solves in its timed sample")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -154,6 +161,59 @@ def heat_fwd_adjoint(cyl, torch, synth, reps, size=192, steps=200, every=20):
     return res
 
 
+def batched_heat(cyl, torch, synth, count, steps):
+    """64 uneven BDF1 heat problems: per-problem stepping vs one batch."""
+    S = synth.SEED_BASE
+    specs = synth.batch_specs(S + 10, count=count)
+    t0 = time.perf_counter()
+    plans, heats = [], []
+    for i, (m, n, p, alpha) in enumerate(specs):
+        pl = cyl.Plan(m, n, p)
+        T0 = torch.from_numpy(synth.eigenmode_values(synth.eigenmode_params(S + 10 + i), m, n, p)).cuda()
+        g = pl.transform_inv(torch.from_numpy(synth.smooth_coeffs(m, n, p, S + 100 + i)).cuda())
+        heats.append(cyl.Heat(pl, [T0], g, alpha, 1e-3, 1, 1e-12))
+        plans.append(pl)
+        del T0, g
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    for h in heats:
+        h.step(1)                              # warm-up: first launches of every size
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for h in heats:
+        h.step(steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batch = cyl.Batch(heats)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    batch.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    info = batch.describe()
+    unknowns = sum(m * n * p for m, n, p, _ in specs)
+    res = {"problem_steps_per_s": count * steps / t_batch, "ms_per_batched_step": 1e3 * t_batch / steps,
+           "plain_problem_steps_per_s": count * steps / t_plain, "plain_ms_per_step_all": 1e3 * t_plain / steps,
+           "speedup_vs_plain": t_plain / t_batch, "unknowns_per_step": unknowns,
+           "unknowns_per_s": unknowns * steps / t_batch,
+           "launches_per_adi_pass": info["launches_per_pass"], "graph": info["graph"],
+           "grouping": info["grouping"], "setup_s": t_setup, "batch_create_s": t_create,
+           "config": {"workload": "batched_heat_%d_uneven" % count, "problems": count, "steps": steps,
+                      "n_r=n_z": [min(s[0] for s in specs), max(s[0] for s in specs)],
+                      "n_theta": [min(s[2] for s in specs), max(s[2] for s in specs)],
+                      "alpha": [0.1, 2.0], "dt": 1e-3, "bdf": 1, "adi_tol": 1e-12}}
+    batch.close()
+    for h in heats:
+        h.close()
+    for pl in plans:
+        pl.close()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -237,6 +297,10 @@ def main():
 
     if not args.no_adjoint:
         out["heat_fwd_adjoint_192"] = heat_fwd_adjoint(cyl, torch, synth, args.adjoint_reps)
+
+    if not args.no_batch:
+        print("bench: batched heat leg", file=sys.stderr, flush=True)
+        out["batched_64"] = batched_heat(cyl, torch, synth, args.batch_count, args.batch_steps)
 
     if args.calibrate_copy:
         a = torch.ones(1 << 26, dtype=torch.float64, device="cuda")

@@ -45,6 +45,7 @@ extern "C" {
 typedef struct cyl_plan_s* cyl_plan_t;
 typedef struct cyl_heat_s* cyl_heat_t;
 typedef struct cyl_heat_grad_s* cyl_heat_grad_t;
+typedef struct cyl_batch_s* cyl_batch_t;
 
 enum {
     CYL_OK = 0,
@@ -162,6 +163,34 @@ int cyl_heat_grad_forward(cyl_heat_grad_t a);
 int cyl_heat_grad_backward(cyl_heat_grad_t a, int space, const double* T_bar, double* T0_bar,
                            double* g_bar, double* alpha_bar);
 int cyl_heat_grad_destroy(cyl_heat_grad_t a);
+
+/* Batched heat stepping over independent problems of uneven sizes (the
+ * per-mode solves of Section 3 are independent within a problem and across
+ * problems).  A batch step runs, for every member, the heat right side, the
+ * ADI passes (and residual correction) and the history projection of
+ * cyl_heat_step, but as a few launches over all members: one heat-right-side
+ * launch, per ADI pass a few launches that take the parity blocks of all
+ * members sorted by cost J(w) m_e n_e, one residual and one projection launch.
+ * Results are identical to stepping every member with cyl_heat_step.
+ *
+ * cyl_batch_create: count >= 1 distinct heat handles whose plans share one
+ *   stream.  The batch owns a right-side and a residual workspace per member
+ *   (2 E-layout fields each), its own HIP stream and, unless
+ *   CYL_BATCH_NO_GRAPH, a HIP graph of one step cycle (lcm of the members'
+ *   BDF orders) that cyl_batch_step replays.  Unless CYL_BATCH_NO_TUNE, it
+ *   times the candidate launch groupings once (cached per batch signature for
+ *   the process) and keeps the fastest.
+ * cyl_batch_step: advance every member n_steps (enqueue only; ordered after
+ *   earlier work on the members' stream and before later work on it).
+ *   Members must not be stepped by other calls while in the batch
+ *   (CYL_E_INVALID_ARG).  Results are read with cyl_heat_read.
+ * cyl_batch_describe: launches per ADI pass, whether a graph is replayed, and
+ *   the chosen grouping (a static string owned by the batch). */
+enum { CYL_BATCH_NO_GRAPH = 1, CYL_BATCH_NO_TUNE = 2 };
+int cyl_batch_create(cyl_batch_t* b, int count, const cyl_heat_t* heats, int flags);
+int cyl_batch_step(cyl_batch_t b, int n_steps);
+int cyl_batch_describe(cyl_batch_t b, int* launches_per_pass, int* uses_graph, const char** grouping);
+int cyl_batch_destroy(cyl_batch_t b);
 
 /* Host-only (needs no GPU): the ADI parameters the plan would use for
  * wavenumber w of an n_r x n_z grid.  kappa_alpha = 0 selects the Poisson

@@ -29,7 +29,11 @@ EXPORTS = ["cyl_plan_create", "cyl_plan_destroy", "cyl_transform_fwd", "cyl_tran
            "cyl_heat_destroy", "cyl_adi_parameters", "cyl_plan_set_profiling",
            "cyl_plan_get_profile", "cyl_status_string", "cyl_last_error",
            "cyl_transform_fwd_adjoint", "cyl_transform_inv_adjoint", "cyl_heat_grad_create",
-           "cyl_heat_grad_forward", "cyl_heat_grad_backward", "cyl_heat_grad_destroy"]
+           "cyl_heat_grad_forward", "cyl_heat_grad_backward", "cyl_heat_grad_destroy",
+           "cyl_batch_create", "cyl_batch_step", "cyl_batch_describe", "cyl_batch_destroy"]
+
+CYL_BATCH_NO_GRAPH = 1
+CYL_BATCH_NO_TUNE = 2
 
 
 class CylError(RuntimeError):
@@ -88,6 +92,10 @@ def load():
         "cyl_heat_grad_forward": [P],
         "cyl_heat_grad_backward": [P, I, P, P, P, P],
         "cyl_heat_grad_destroy": [P],
+        "cyl_batch_create": [ctypes.POINTER(P), I, ctypes.POINTER(P), I],
+        "cyl_batch_step": [P, I],
+        "cyl_batch_describe": [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(ctypes.c_char_p)],
+        "cyl_batch_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -303,6 +311,43 @@ class HeatGrad:
     def close(self):
         if self._h:
             _check(self._lib.cyl_heat_grad_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Batched stepping of several ``Heat`` handles (uneven sizes) in few launches.
+
+    ``graph``: replay a captured HIP graph of one step cycle; ``tune``: time the
+    candidate launch groupings once and keep the fastest.
+    """
+
+    def __init__(self, heats, graph=True, tune=True):
+        self.heats = list(heats)
+        self._lib = self.heats[0]._lib
+        arr = (ctypes.c_void_p * len(self.heats))(*[h._h.value for h in self.heats])
+        flags = (0 if graph else CYL_BATCH_NO_GRAPH) | (0 if tune else CYL_BATCH_NO_TUNE)
+        self._h = ctypes.c_void_p()
+        _check(self._lib.cyl_batch_create(ctypes.byref(self._h), len(self.heats), arr, flags))
+
+    def step(self, n_steps=1):
+        _check(self._lib.cyl_batch_step(self._h, int(n_steps)))
+
+    def describe(self):
+        n = ctypes.c_int()
+        g = ctypes.c_int()
+        s = ctypes.c_char_p()
+        _check(self._lib.cyl_batch_describe(self._h, ctypes.byref(n), ctypes.byref(g), ctypes.byref(s)))
+        return {"launches_per_pass": n.value, "graph": bool(g.value), "grouping": s.value.decode()}
+
+    def close(self):
+        if self._h:
+            _check(self._lib.cyl_batch_destroy(self._h))
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -264,9 +264,13 @@ template <int NP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_adi_lds(const BlockDesc* __restrict__ blocks, const double* __restrict__ E, double* X,
                const double* __restrict__ rtab, const double* __restrict__ ztab,
-               const double* __restrict__ vmu, int accumulate) {
+               const double* __restrict__ vmu, int accumulate, const AdiPtrs* __restrict__ pp) {
     extern __shared__ double sm[];
     const BlockDesc bd = blocks[blockIdx.x];
+    if (pp != nullptr) {
+        const AdiPtrs q = pp[bd.prob];
+        E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
+    }
     adi_block_lds<NP + 1>(sm, bd, E, X, rtab, ztab, vmu, accumulate);
 }
 
@@ -763,9 +767,13 @@ template <int NP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_adi_split(const BlockDesc* __restrict__ blocks, const double* __restrict__ E, double* X,
                  const double* __restrict__ rtab, const double* __restrict__ ztab,
-                 const double* __restrict__ vmu, int accumulate) {
+                 const double* __restrict__ vmu, int accumulate, const AdiPtrs* __restrict__ pp) {
     extern __shared__ double sm[];
     const BlockDesc bd = blocks[blockIdx.x];
+    if (pp != nullptr) {
+        const AdiPtrs q = pp[bd.prob];
+        E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
+    }
     adi_block_split<NP + 1>(sm, bd, E, X, rtab, ztab, vmu, accumulate);
 }
 
@@ -848,8 +856,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void k_adi_global(const BlockDesc* __restrict__ blocks, const double* __restrict__ E, double* X,
                   double* state, int64_t state_stride, const double* __restrict__ rtab,
                   const double* __restrict__ ztab, const double* __restrict__ vmu,
-                  int accumulate) {
+                  int accumulate, const AdiPtrs* __restrict__ pp) {
     const BlockDesc bd = blocks[blockIdx.x];
+    if (pp != nullptr) {
+        const AdiPtrs q = pp[bd.prob];
+        E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
+    }
     const int me = bd.me, ne = bd.ne, mp = bd.mp, np = bd.np;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int ld = np + 1;
@@ -1057,18 +1069,14 @@ constexpr int kTile = 32;
 constexpr int kTR = kTile + 5, kTC = kTile + 3;
 constexpr int kTS = kTC + 2;          // odd LDS row length (conflict-free row reads)
 
-__global__ __launch_bounds__(256) void k_apply(const BlockDesc* __restrict__ blocks,
-                                               const double* __restrict__ E, double sE,
-                                               const double* __restrict__ X, double sAB,
-                                               double sCD, double* __restrict__ out,
-                                               const double* __restrict__ atab, int64_t a_wstride,
-                                               int me0, const double* __restrict__ ztabA, int ne0) {
-    __shared__ double xs[kTR * kTS];
-    __shared__ double zs[kTile * 8];
-    const BlockDesc bd = blocks[blockIdx.z];
+// One 32 x 32 output tile (i0, k0) of block bd; xs, zs: LDS scratch.
+__device__ __forceinline__ void apply_tile(double* xs, double* zs, const BlockDesc& bd, int i0, int k0,
+                                           const double* __restrict__ E, double sE,
+                                           const double* __restrict__ X, double sAB, double sCD,
+                                           double* __restrict__ out, const double* __restrict__ atab,
+                                           int64_t a_wstride, int me0,
+                                           const double* __restrict__ ztabA, int ne0) {
     const int me = bd.me, ne = bd.ne;
-    const int i0 = blockIdx.x * kTile, k0 = blockIdx.y * kTile;
-    if (i0 >= me || k0 >= ne) return;
     const int tid = threadIdx.x;
     const double* Xb = X + bd.xoff;
     for (int idx = tid; idx < kTR * kTC; idx += blockDim.x) {
@@ -1113,6 +1121,33 @@ __global__ __launch_bounds__(256) void k_apply(const BlockDesc* __restrict__ blo
     }
 }
 
+__global__ __launch_bounds__(256) void k_apply(const BlockDesc* __restrict__ blocks,
+                                               const double* __restrict__ E, double sE,
+                                               const double* __restrict__ X, double sAB,
+                                               double sCD, double* __restrict__ out,
+                                               const double* __restrict__ atab, int64_t a_wstride,
+                                               int me0, const double* __restrict__ ztabA, int ne0) {
+    __shared__ double xs[kTR * kTS];
+    __shared__ double zs[kTile * 8];
+    const BlockDesc bd = blocks[blockIdx.z];
+    const int i0 = blockIdx.x * kTile, k0 = blockIdx.y * kTile;
+    if (i0 >= bd.me || k0 >= bd.ne) return;
+    apply_tile(xs, zs, bd, i0, k0, E, sE, X, sAB, sCD, out, atab, a_wstride, me0, ztabA, ne0);
+}
+
+__global__ __launch_bounds__(256) void k_apply_batch(const ApplyItem* __restrict__ items,
+                                                     const BlockDesc* __restrict__ blocks,
+                                                     const ApplyPtrs* __restrict__ pp, double sE,
+                                                     double sAB, double sCD) {
+    __shared__ double xs[kTR * kTS];
+    __shared__ double zs[kTile * 8];
+    const ApplyItem it = items[blockIdx.x];
+    const BlockDesc bd = blocks[it.block];
+    const ApplyPtrs q = pp[bd.prob];
+    apply_tile(xs, zs, bd, it.ti * kTile, it.tk * kTile, q.E, sE, q.X, sAB, sCD, q.out, q.atab,
+               q.a_wstride, q.me0, q.ztabA, q.ne0);
+}
+
 struct PList { const double* p[4]; double beta[4]; };
 
 __global__ __launch_bounds__(256) void k_heat_rhs(double* __restrict__ E, PList P, int nb,
@@ -1122,6 +1157,29 @@ __global__ __launch_bounds__(256) void k_heat_rhs(double* __restrict__ E, PList 
     double acc = Ec[e];
     for (int b = 0; b < nb; ++b) acc += P.beta[b] * P.p[b][e];
     E[e] = acc;
+}
+
+// Batched heat right side: workgroup g belongs to the item q with
+// wg_start[q] <= g < wg_start[q + 1]; 256 threads x 4 elements per workgroup.
+__global__ __launch_bounds__(256) void k_heat_rhs_batch(const HeatRhsItem* __restrict__ items,
+                                                        int nitems,
+                                                        const int64_t* __restrict__ wg_start) {
+    const int64_t g = blockIdx.x;
+    int lo = 0, hi = nitems;                 // wg_start[lo] <= g < wg_start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (wg_start[mid] <= g) lo = mid; else hi = mid;
+    }
+    const HeatRhsItem it = items[lo];
+    const int64_t base = (g - wg_start[lo]) * 1024 + threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int64_t e = base + c * 256;
+        if (e >= it.total) break;
+        double acc = it.Ec[e];
+        for (int b = 0; b < it.nb; ++b) acc += it.beta[b] * it.P[b][e];
+        it.E[e] = acc;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_norms(const double* __restrict__ R,
@@ -1151,9 +1209,9 @@ __global__ __launch_bounds__(256) void k_norms(const double* __restrict__ R,
 template <int NP>
 hipError_t launch_lds(const BlockDesc* blocks, int nblocks, int threads, const double* E,
                       double* X, const double* rtab, const double* ztab, const double* vmu,
-                      bool accumulate, size_t lds_bytes, hipStream_t s) {
+                      bool accumulate, size_t lds_bytes, hipStream_t s, const AdiPtrs* pp) {
     hipLaunchKernelGGL(k_adi_lds<NP>, dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
-                       rtab, ztab, vmu, accumulate ? 1 : 0);
+                       rtab, ztab, vmu, accumulate ? 1 : 0, pp);
     return hipGetLastError();
 }
 
@@ -1166,9 +1224,9 @@ hipError_t set_limit(size_t bytes) {
 template <int NP>
 hipError_t launch_split(const BlockDesc* blocks, int nblocks, int threads, const double* E,
                         double* X, const double* rtab, const double* ztab, const double* vmu,
-                        bool accumulate, size_t lds_bytes, hipStream_t s) {
+                        bool accumulate, size_t lds_bytes, hipStream_t s, const AdiPtrs* pp) {
     hipLaunchKernelGGL(k_adi_split<NP>, dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
-                       rtab, ztab, vmu, accumulate ? 1 : 0);
+                       rtab, ztab, vmu, accumulate ? 1 : 0, pp);
     return hipGetLastError();
 }
 
@@ -1186,17 +1244,17 @@ hipError_t set_split_limit(size_t bytes) {
 hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, int np0, const double* E,
                       double* X, double* state, int64_t state_stride, const double* rtab,
                       const double* ztab, const double* vmu, bool accumulate, bool use_lds,
-                      size_t lds_bytes, hipStream_t s) {
+                      size_t lds_bytes, hipStream_t s, const AdiPtrs* pp) {
     if (use_lds) {
         switch (np0) {
-#define CYL_CASE(v) case v: return launch_lds<v>(blocks, nblocks, threads, E, X, rtab, ztab, vmu, accumulate, lds_bytes, s);
+#define CYL_CASE(v) case v: return launch_lds<v>(blocks, nblocks, threads, E, X, rtab, ztab, vmu, accumulate, lds_bytes, s, pp);
             CYL_NP_CASES(CYL_CASE)
 #undef CYL_CASE
             default: return hipErrorInvalidValue;
         }
     }
     hipLaunchKernelGGL(k_adi_global, dim3(nblocks), dim3(threads), 0, s, blocks, E, X, state,
-                       state_stride, rtab, ztab, vmu, accumulate ? 1 : 0);
+                       state_stride, rtab, ztab, vmu, accumulate ? 1 : 0, pp);
     return hipGetLastError();
 }
 
@@ -1209,10 +1267,11 @@ size_t adi_split_lds_bytes(int mp0, int np0) {
 
 hipError_t launch_adi_split(const BlockDesc* blocks, int nblocks, int threads, int np0,
                             const double* E, double* X, const double* rtab, const double* ztab,
-                            const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s) {
+                            const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
+                            const AdiPtrs* pp) {
     if (threads < 128 || threads > 256 || threads % 128 != 0) return hipErrorInvalidValue;
     switch (np0) {
-#define CYL_CASE(v) case v: return launch_split<v>(blocks, nblocks, threads, E, X, rtab, ztab, vmu, accumulate, lds_bytes, s);
+#define CYL_CASE(v) case v: return launch_split<v>(blocks, nblocks, threads, E, X, rtab, ztab, vmu, accumulate, lds_bytes, s, pp);
         CYL_NP_CASES(CYL_CASE)
 #undef CYL_CASE
         default: return hipErrorInvalidValue;
@@ -1280,6 +1339,22 @@ hipError_t launch_apply2(const BlockDesc* blocks, int nblocks, int me0, int ne0,
                     static_cast<unsigned>((ne0 + kTile - 1) / kTile), nblocks);
     hipLaunchKernelGGL(k_apply, grid, dim3(256), 0, s, blocks, E, sE, X, sAB, sCD, out, atab,
                        a_wstride, me0, ztabA, ne0);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_batch(const ApplyItem* items, int nitems, const BlockDesc* blocks,
+                              const ApplyPtrs* pp, double sE, double sAB, double sCD, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_apply_batch, dim3(static_cast<unsigned>(nitems)), dim3(256), 0, s, items, blocks, pp,
+                       sE, sAB, sCD);
+    return hipGetLastError();
+}
+
+hipError_t launch_heat_rhs_batch(const HeatRhsItem* items, int nitems, const int64_t* wg_start,
+                                 int64_t nwg, hipStream_t s) {
+    if (nitems <= 0 || nwg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_heat_rhs_batch, dim3(static_cast<unsigned>(nwg)), dim3(256), 0, s, items, nitems,
+                       wg_start);
     return hipGetLastError();
 }
 

@@ -10,6 +10,9 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <sstream>
+#include <tuple>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -166,6 +169,50 @@ struct cyl_heat_grad_s {
     DevMem atab_pois, proj_flip;        // Poisson apply rows; flipped projection rows
     DevMem ckpt, seg, Pw, Xh, Et, Gsum, partials, planes, vals;
     int64_t ck_stride = 0, n_partials = 0;
+};
+
+// One launch of a batched ADI pass: every block of the group, cost-sorted.
+struct BatchLaunch {
+    int kind = 0;                 // 0 split sweeps, 1 LDS one thread per line, 2 HBM state
+    int np = 0, threads = 0;
+    size_t lds = 0;
+    int nblocks = 0;
+    int64_t state_stride = 0;
+    std::unique_ptr<cyl::DevMem> blocks, state;
+};
+
+// Batched heat stepping over independent problems (uneven sizes).
+struct cyl_batch_s {
+    hipStream_t user = nullptr;          // the stream of every member's plan
+    hipStream_t stream = nullptr;        // the batch's own stream (capturable)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<cyl_heat_t> heats;
+    std::vector<int> head0;              // heads the cycle tables were built for
+    std::vector<long long> steps0;
+    int L = 1, pos = 0;                  // steps per cycle; position of the next step
+    long long taken = 0;                 // steps advanced by the batch
+    std::vector<std::unique_ptr<cyl::DevMem>> E, R;   // per-problem right side / residual
+    std::vector<BatchLaunch> adi1, adi2; // pass 1 (all), pass 2 (two-pass problems)
+    cyl::DevMem ptr1, ptr2;              // AdiPtrs per problem for the two passes
+    cyl::DevMem blocks_all;              // every block, prob set (apply items index it)
+    cyl::DevMem res_items, res_ptrs;
+    int n_res = 0;
+    cyl::DevMem proj_items;
+    int n_proj = 0;
+    std::vector<std::unique_ptr<cyl::DevMem>> proj_ptrs, rhs_items;   // per cycle position
+    cyl::DevMem rhs_wg;
+    int64_t rhs_nwg = 0;
+    std::string grouping;
+    bool use_graph = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~cyl_batch_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
 };
 
 namespace cyl {
@@ -602,6 +649,255 @@ void heat_step_bdf1(cyl_heat_t h, const double* Pin, double* X, double* Pout) {
     hip_check(launch_apply2(s->blocks.as<BlockDesc>(), static_cast<int>(s->hblocks.size()), g.me[0], g.ne[0],
                             nullptr, 0.0, X, -1.0, 0.0, Pout, pl->atab_proj.as<double>(), 0,
                             pl->ztabA.as<double>(), pl->stream), "project");
+}
+
+// ---------------------------------------------------------------------------
+// batched heat stepping
+// ---------------------------------------------------------------------------
+int adi_kind(const cyl_plan_s* pl) { return pl->adi_split ? 0 : (pl->use_lds ? 1 : 2); }
+
+struct BlockRef {
+    BlockDesc b;
+    double cost;
+    int kind, threads, np, mp;
+    int64_t sstride;
+};
+
+// Launch groups of one ADI pass.  grouping 0: one launch per (kernel, threads);
+// 1: one per (kernel, threads, padded width); 2: one per kernel.  Blocks of a
+// launch are sorted by cost (J me ne) so that the dispatcher hands the
+// longest blocks out first.
+std::vector<BatchLaunch> build_launches(const std::vector<BlockRef>& refs, int grouping) {
+    std::map<std::tuple<int, int, int>, std::vector<const BlockRef*>> groups;
+    for (const auto& r : refs) {
+        const std::tuple<int, int, int> key =
+            grouping == 0 ? std::make_tuple(r.kind, r.threads, 0)
+                          : grouping == 1 ? std::make_tuple(r.kind, r.threads, r.np) : std::make_tuple(r.kind, 0, 0);
+        groups[key].push_back(&r);
+    }
+    auto chunks = [](int x) { return static_cast<size_t>((x + 127) / 128 * 128); };
+    std::vector<BatchLaunch> out;
+    for (auto& kv : groups) {
+        auto& v = kv.second;
+        std::stable_sort(v.begin(), v.end(), [](const BlockRef* a, const BlockRef* b) { return a->cost > b->cost; });
+        BatchLaunch l;
+        l.kind = v.front()->kind;
+        int mp = 0;
+        for (const BlockRef* r : v) {
+            l.threads = std::max(l.threads, r->threads);
+            l.np = std::max(l.np, r->np);
+            mp = std::max(mp, r->mp);
+            l.state_stride = std::max(l.state_stride, r->sstride);
+        }
+        l.nblocks = static_cast<int>(v.size());
+        if (l.kind == 0) {
+            l.lds = adi_split_lds_bytes(mp, l.np);
+            if (l.lds > 65536) hip_check(adi_split_set_lds_limit(l.np, l.lds), "LDS limit");
+        } else if (l.kind == 1) {
+            l.lds = (static_cast<size_t>(mp + 4) * (l.np + 1) + chunks(kRRec * mp) + chunks(kZRec * l.np)) * sizeof(double);
+            if (l.lds > 65536) hip_check(adi_set_lds_limit(l.np, l.lds), "LDS limit");
+        } else {
+            l.state = std::make_unique<DevMem>();
+            l.state->alloc(static_cast<size_t>(l.nblocks) * l.state_stride * sizeof(double));
+        }
+        std::vector<BlockDesc> hb;
+        hb.reserve(v.size());
+        for (const BlockRef* r : v) hb.push_back(r->b);
+        l.blocks = std::make_unique<DevMem>();
+        upload(*l.blocks, hb);
+        out.push_back(std::move(l));
+    }
+    return out;
+}
+
+void run_adi_launches(hipStream_t st, const std::vector<BatchLaunch>& ls, const AdiPtrs* pp, bool acc) {
+    for (const auto& l : ls) {
+        const BlockDesc* bl = l.blocks->as<BlockDesc>();
+        if (l.kind == 0)
+            hip_check(launch_adi_split(bl, l.nblocks, l.threads, l.np, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                       acc, l.lds, st, pp), "batched adi");
+        else
+            hip_check(launch_adi(bl, l.nblocks, l.threads, l.np, nullptr, nullptr,
+                                 l.state ? l.state->as<double>() : nullptr, l.state_stride, nullptr, nullptr,
+                                 nullptr, acc, l.kind == 1, l.lds, st, pp), "batched adi");
+    }
+}
+
+// One batched BDF step at cycle position c (enqueue only).
+void batch_step_once(cyl_batch_s* B, int c) {
+    const int nprob = static_cast<int>(B->heats.size());
+    hip_check(launch_heat_rhs_batch(B->rhs_items[c]->as<HeatRhsItem>(), nprob, B->rhs_wg.as<int64_t>(),
+                                    B->rhs_nwg, B->stream), "batched heat rhs");
+    run_adi_launches(B->stream, B->adi1, B->ptr1.as<AdiPtrs>(), false);
+    if (B->n_res > 0) {
+        hip_check(launch_apply_batch(B->res_items.as<ApplyItem>(), B->n_res, B->blocks_all.as<BlockDesc>(),
+                                     B->res_ptrs.as<ApplyPtrs>(), 1.0, 1.0, 1.0, B->stream), "batched residual");
+        run_adi_launches(B->stream, B->adi2, B->ptr2.as<AdiPtrs>(), true);
+    }
+    hip_check(launch_apply_batch(B->proj_items.as<ApplyItem>(), B->n_proj, B->blocks_all.as<BlockDesc>(),
+                                 B->proj_ptrs[c]->as<ApplyPtrs>(), 0.0, -1.0, 0.0, B->stream), "batched projection");
+}
+
+// Host bookkeeping of the members after one step.
+void batch_advance(cyl_batch_s* B) {
+    for (cyl_heat_t h : B->heats) {
+        h->head = (h->head + h->order - 1) % h->order;
+        ++h->steps;
+    }
+    B->pos = (B->pos + 1) % B->L;
+    ++B->taken;
+}
+
+std::mutex g_tune_mutex;
+std::map<std::string, int> g_tune_cache;
+
+// Time one pass-1 ADI with each grouping on scratch outputs; keep the fastest.
+int autotune_grouping(cyl_batch_s* B, const std::vector<BlockRef>& refs, const std::string& key) {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) return it->second;
+    }
+    const int nprob = static_cast<int>(B->heats.size());
+    std::vector<AdiPtrs> tp(nprob);
+    for (int q = 0; q < nprob; ++q) {
+        Setup* s = B->heats[q]->setup.get();
+        tp[q] = AdiPtrs{B->E[q]->as<double>(), B->R[q]->as<double>(), s->rtab.as<double>(), s->ztab.as<double>(),
+                        s->vmu.as<double>()};
+    }
+    DevMem tpd;
+    upload(tpd, tp);
+    hipEvent_t a, b;
+    hip_check(hipEventCreate(&a), "hipEventCreate");
+    hip_check(hipEventCreate(&b), "hipEventCreate");
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int grouping = 0; grouping < 3; ++grouping) {
+        const auto ls = build_launches(refs, grouping);
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            hip_check(hipEventRecord(a, B->stream), "hipEventRecord");
+            run_adi_launches(B->stream, ls, tpd.as<AdiPtrs>(), false);
+            hip_check(hipEventRecord(b, B->stream), "hipEventRecord");
+            hip_check(hipEventSynchronize(b), "hipEventSynchronize");
+            float t = 0.0f;
+            hip_check(hipEventElapsedTime(&t, a, b), "hipEventElapsedTime");
+            ms = std::min(ms, t);
+        }
+        if (ms < best_ms) { best_ms = ms; best = grouping; }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    g_tune_cache[key] = best;
+    return best;
+}
+
+void batch_build(cyl_batch_s* B, int flags) {
+    const int nprob = static_cast<int>(B->heats.size());
+    int L = 1;
+    for (cyl_heat_t h : B->heats) L = std::max(L, h->order);      // orders are 1 or 4
+    B->L = L;
+    hip_check(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking), "hipStreamCreate");
+    hip_check(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming), "hipEventCreate");
+    hip_check(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming), "hipEventCreate");
+    std::vector<BlockRef> refs1, refs2;
+    std::vector<BlockDesc> all;
+    std::vector<ApplyItem> res_items, proj_items;
+    std::vector<AdiPtrs> p1(nprob), p2(nprob);
+    std::vector<ApplyPtrs> rp(nprob);
+    std::vector<std::vector<ApplyPtrs>> pp(L, std::vector<ApplyPtrs>(nprob));
+    std::vector<std::vector<HeatRhsItem>> ri(L, std::vector<HeatRhsItem>(nprob));
+    std::vector<int64_t> wg(nprob + 1, 0);
+    std::ostringstream key;
+    for (int q = 0; q < nprob; ++q) {
+        cyl_heat_t h = B->heats[q];
+        cyl_plan_s* pl = h->plan;
+        const Geometry& g = pl->geo;
+        Setup* s = h->setup.get();
+        B->E.push_back(std::make_unique<DevMem>());
+        B->R.push_back(std::make_unique<DevMem>());
+        alloc_elayout(*B->E.back(), g);
+        alloc_elayout(*B->R.back(), g);
+        double* Eq = B->E.back()->as<double>();
+        double* Rq = B->R.back()->as<double>();
+        double* Xq = h->Xt.as<double>();
+        p1[q] = AdiPtrs{Eq, Xq, s->rtab.as<double>(), s->ztab.as<double>(), s->vmu.as<double>()};
+        p2[q] = AdiPtrs{Rq, Xq, s->rtab.as<double>(), s->ztab.as<double>(), s->vmu.as<double>()};
+        rp[q] = ApplyPtrs{Eq, Xq, Rq, s->atab.as<double>(), s->ztabA,
+                          static_cast<int64_t>(g.me[0] + g.me[1]) * 12, g.me[0], g.ne[0]};
+        const int kind = adi_kind(pl);
+        const int lines = ((std::max(g.me[0], g.ne[0]) + 63) / 64) * 64;
+        const int threads = kind == 0 ? 2 * lines : std::min(512, lines);
+        key << kind << ':' << g.np[0] << ':' << g.mp[0] << ':' << s->hblocks.size() << ':' << s->passes << ';';
+        for (const BlockDesc& b0 : s->hblocks) {
+            BlockDesc b = b0;
+            b.prob = q;
+            const int bi = static_cast<int>(all.size());
+            all.push_back(b);
+            BlockRef r{b, static_cast<double>(b.J) * b.me * b.ne, kind, threads, g.np[0], g.mp[0],
+                       static_cast<int64_t>(g.mp[0] + 4) * (g.np[0] + 1)};
+            refs1.push_back(r);
+            if (s->passes == 2) refs2.push_back(r);
+            for (int ti = 0; ti * 32 < b.me; ++ti)
+                for (int tk = 0; tk * 32 < b.ne; ++tk) {
+                    proj_items.push_back(ApplyItem{bi, ti, tk, 0});
+                    if (s->passes == 2) res_items.push_back(ApplyItem{bi, ti, tk, 0});
+                }
+        }
+        // cycle tables: the head moves down by one (mod order) every step
+        for (int c = 0; c < L; ++c) {
+            const int hc = ((h->head - c) % h->order + h->order) % h->order;
+            HeatRhsItem it{};
+            it.E = Eq;
+            for (int i = 0; i < h->order; ++i) {
+                it.P[i] = h->P[(hc + i) % h->order].as<double>();
+                it.beta[i] = h->beta[i];
+            }
+            it.nb = h->order;
+            it.Ec = h->Econst.as<double>();
+            it.total = g.etotal_elems;
+            ri[c][q] = it;
+            const int slot = (hc + h->order - 1) % h->order;
+            pp[c][q] = ApplyPtrs{nullptr, Xq, h->P[slot].as<double>(), pl->atab_proj.as<double>(),
+                                 pl->ztabA.as<double>(), 0, g.me[0], g.ne[0]};
+        }
+        wg[q + 1] = wg[q] + (g.etotal_elems + 1023) / 1024;
+        B->head0.push_back(h->head);
+        B->steps0.push_back(h->steps);
+    }
+    B->rhs_nwg = wg[nprob];
+    upload(B->rhs_wg, wg);
+    for (int c = 0; c < L; ++c) {
+        B->rhs_items.push_back(std::make_unique<DevMem>());
+        upload(*B->rhs_items.back(), ri[c]);
+        B->proj_ptrs.push_back(std::make_unique<DevMem>());
+        upload(*B->proj_ptrs.back(), pp[c]);
+    }
+    upload(B->ptr1, p1);
+    upload(B->ptr2, p2);
+    upload(B->res_ptrs, rp);
+    upload(B->blocks_all, all);
+    upload(B->res_items, res_items);
+    upload(B->proj_items, proj_items);
+    B->n_res = static_cast<int>(res_items.size());
+    B->n_proj = static_cast<int>(proj_items.size());
+    // launch grouping: forced, tuned (cached per batch signature), or one per (kernel, threads)
+    int grouping = env_int("CYLSPEC_BATCH_GROUPING", -1);
+    if (grouping < 0 || grouping > 2)
+        grouping = (flags & CYL_BATCH_NO_TUNE) ? 0 : autotune_grouping(B, refs1, key.str());
+    static const char* names[3] = {"per kernel and thread count", "per kernel, thread count and width",
+                                   "per kernel"};
+    B->grouping = names[grouping];
+    B->adi1 = build_launches(refs1, grouping);
+    if (!refs2.empty()) B->adi2 = build_launches(refs2, grouping);
+    B->use_graph = (flags & CYL_BATCH_NO_GRAPH) == 0;
+    if (B->use_graph) {
+        hip_check(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        for (int c = 0; c < L; ++c) batch_step_once(B, c);
+        hip_check(hipStreamEndCapture(B->stream, &B->graph), "hipStreamEndCapture");
+        hip_check(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    }
 }
 
 double* ckpt_slot(cyl_heat_grad_s* a, int j) { return a->ckpt.as<double>() + j * a->ck_stride; }
@@ -1068,6 +1364,81 @@ int cyl_heat_grad_destroy(cyl_heat_grad_t a) {
         if (!a) fail(CYL_E_INVALID_ARG, "handle is NULL");
         (void)hipStreamSynchronize(a->stream);
         delete a;
+    });
+}
+
+int cyl_batch_create(cyl_batch_t* out, int count, const cyl_heat_t* heats, int flags) {
+    cyl_batch_s* raw = nullptr;
+    const int st = guarded([&] {
+        if (!out) fail(CYL_E_INVALID_ARG, "batch pointer is NULL");
+        *out = nullptr;
+        if (count < 1 || !heats) fail(CYL_E_INVALID_ARG, "need count >= 1 heat handles");
+        if (flags & ~(CYL_BATCH_NO_GRAPH | CYL_BATCH_NO_TUNE)) fail(CYL_E_INVALID_ARG, "unknown flags");
+        auto B = std::make_unique<cyl_batch_s>();
+        for (int i = 0; i < count; ++i) {
+            if (!heats[i]) fail(CYL_E_INVALID_ARG, "NULL heat handle");
+            for (int j = 0; j < i; ++j)
+                if (heats[j] == heats[i]) fail(CYL_E_INVALID_ARG, "a heat handle appears twice");
+            if (heats[i]->stream != heats[0]->stream) fail(CYL_E_INVALID_ARG, "member plans use different streams");
+            B->heats.push_back(heats[i]);
+        }
+        B->user = heats[0]->stream;
+        batch_build(B.get(), flags);
+        raw = B.release();
+    });
+    if (st == CYL_OK) *out = raw;
+    return st;
+}
+
+int cyl_batch_step(cyl_batch_t b, int n_steps) {
+    return guarded([&] {
+        if (!b) fail(CYL_E_INVALID_ARG, "batch is NULL");
+        if (n_steps < 0) fail(CYL_E_INVALID_ARG, "n_steps must be >= 0");
+        const int nprob = static_cast<int>(b->heats.size());
+        for (int q = 0; q < nprob; ++q) {
+            cyl_heat_t h = b->heats[q];
+            const int expect = static_cast<int>(((b->head0[q] - b->taken) % h->order + h->order) % h->order);
+            if (h->steps != b->steps0[q] + b->taken || h->head != expect)
+                fail(CYL_E_INVALID_ARG, "a member was stepped outside the batch");
+        }
+        if (n_steps == 0) return;
+        hip_check(hipEventRecord(b->ev_in, b->user), "hipEventRecord");
+        hip_check(hipStreamWaitEvent(b->stream, b->ev_in, 0), "hipStreamWaitEvent");
+        int left = n_steps;
+        while (left > 0 && (b->pos != 0 || !b->use_graph || left < b->L)) {
+            batch_step_once(b, b->pos);
+            batch_advance(b);
+            --left;
+        }
+        while (left >= b->L) {
+            hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
+            for (int c = 0; c < b->L; ++c) batch_advance(b);
+            left -= b->L;
+        }
+        while (left > 0) {
+            batch_step_once(b, b->pos);
+            batch_advance(b);
+            --left;
+        }
+        hip_check(hipEventRecord(b->ev_out, b->stream), "hipEventRecord");
+        hip_check(hipStreamWaitEvent(b->user, b->ev_out, 0), "hipStreamWaitEvent");
+    });
+}
+
+int cyl_batch_describe(cyl_batch_t b, int* launches_per_pass, int* uses_graph, const char** grouping) {
+    return guarded([&] {
+        if (!b) fail(CYL_E_INVALID_ARG, "batch is NULL");
+        if (launches_per_pass) *launches_per_pass = static_cast<int>(b->adi1.size());
+        if (uses_graph) *uses_graph = b->use_graph ? 1 : 0;
+        if (grouping) *grouping = b->grouping.c_str();
+    });
+}
+
+int cyl_batch_destroy(cyl_batch_t b) {
+    return guarded([&] {
+        if (!b) fail(CYL_E_INVALID_ARG, "batch is NULL");
+        (void)hipStreamSynchronize(b->stream);
+        delete b;
     });
 }
 

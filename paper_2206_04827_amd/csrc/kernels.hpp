@@ -31,10 +31,43 @@ struct BlockDesc {
     int mp, np;              // me, ne rounded up to multiples of 8
     int pr, pz, part, plane;
     int tr, tz;              // split rows of the two-thread sweeps (0: not split)
+    int prob;                // problem index in a batched launch (0 otherwise)
     int64_t eoff, xoff;
     int64_t rbase, zbase;    // offset of (j = 0) records in rtab / ztab
     int64_t rstride, zstride;// record stride between successive shifts
     int64_t soff;            // offset of v_j - u_j values
+};
+
+// Per-problem pointers of a batched launch, indexed by BlockDesc::prob.  When a
+// launcher receives a table, the table's pointers replace the launcher's own.
+struct AdiPtrs {
+    const double* E;
+    double* X;
+    const double* rtab;
+    const double* ztab;
+    const double* vmu;
+};
+struct ApplyPtrs {
+    const double* E;
+    const double* X;
+    double* out;
+    const double* atab;
+    const double* ztabA;
+    int64_t a_wstride;
+    int me0, ne0;
+};
+// One 32 x 32 output tile of a block in a batched apply launch.
+struct ApplyItem {
+    int block, ti, tk, pad;
+};
+// Elementwise heat right side of one problem in a batched launch.
+struct HeatRhsItem {
+    double* E;
+    const double* P[4];
+    double beta[4];
+    const double* Ec;
+    int64_t total;
+    int nb, pad;
 };
 
 // ---- transforms (Section 2) ----
@@ -76,13 +109,14 @@ hipError_t launch_recombine(const double* X, const double2* L, double2* planes,
 hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, int np0, const double* E,
                       double* X, double* state, int64_t state_stride, const double* rtab,
                       const double* ztab, const double* vmu, bool accumulate, bool use_lds,
-                      size_t lds_bytes, hipStream_t s);
+                      size_t lds_bytes, hipStream_t s, const AdiPtrs* pp = nullptr);
 // Split-sweep LDS-resident ADI (tables built with the split layout): two
 // threads per line, 2 * lines threads per workgroup (lines a multiple of 64,
 // at most 128).
 hipError_t launch_adi_split(const BlockDesc* blocks, int nblocks, int threads, int np0,
                             const double* E, double* X, const double* rtab, const double* ztab,
-                            const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s);
+                            const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
+                            const AdiPtrs* pp = nullptr);
 // LDS bytes of the split kernel for padded block sizes mp0 x np0.
 size_t adi_split_lds_bytes(int mp0, int np0);
 
@@ -99,9 +133,18 @@ hipError_t launch_apply2(const BlockDesc* blocks, int nblocks, int me0, int ne0,
                          const double* atab, int64_t a_wstride, const double* ztabA,
                          hipStream_t s);
 
+// Batched apply: one workgroup per item (block, 32 x 32 tile); pointers,
+// records and sizes of each block's problem from pp; sE, sAB, sCD as above.
+hipError_t launch_apply_batch(const ApplyItem* items, int nitems, const BlockDesc* blocks,
+                              const ApplyPtrs* pp, double sE, double sAB, double sCD, hipStream_t s);
+
 // ---- heat ----
 hipError_t launch_heat_rhs(double* E, const double* const* P, const double* beta, int nb,
                            const double* Econst, int64_t total, hipStream_t s);
+// Batched heat right side: wg_start[q] is the first workgroup of item q
+// (nitems + 1 entries, the last one the grid size); 1024 elements per workgroup.
+hipError_t launch_heat_rhs_batch(const HeatRhsItem* items, int nitems, const int64_t* wg_start,
+                                 int64_t nwg, hipStream_t s);
 
 // ---- reductions ----
 // acc[0] += sum R^2, acc[1] += sum E^2 (E-layout, etotal entries),

@@ -89,3 +89,14 @@ def eigenmode_rates(params):
 def half_to_planes(c):
     """Complex half coefficients -> float64 interleaved array (same memory layout)."""
     return np.ascontiguousarray(np.asarray(c, dtype=np.complex128)).view(np.float64)
+
+
+def batch_specs(seed, count=64, n_range=(48, 384), p_range=(32, 256), alpha_range=(0.1, 2.0)):
+    """Sizes and diffusivities of a batch of independent heat problems:
+    n_r = n_z ~ U{n_range}, n_theta ~ U{p_range}, alpha ~ U[alpha_range].
+    Returns a list of (n_r, n_z, n_theta, alpha)."""
+    g = rng(seed)
+    nn = g.integers(n_range[0], n_range[1] + 1, size=count)
+    pp = g.integers(p_range[0], p_range[1] + 1, size=count)
+    aa = g.uniform(alpha_range[0], alpha_range[1], size=count)
+    return [(int(a), int(a), int(b), float(c)) for a, b, c in zip(nn, pp, aa)]

@@ -73,6 +73,13 @@ def test_null_arguments_are_rejected(lib):
     assert lib.cyl_heat_grad_forward(None) == 1
     assert lib.cyl_heat_grad_backward(None, 0, None, None, None, None) == 1
     assert lib.cyl_heat_grad_destroy(None) == 1
+    b = ctypes.c_void_p()
+    assert lib.cyl_batch_create(ctypes.byref(b), 0, None, 0) == 1
+    assert not b.value
+    assert lib.cyl_batch_create(None, 1, None, 0) == 1
+    assert lib.cyl_batch_step(None, 1) == 1
+    assert lib.cyl_batch_describe(None, None, None, None) == 1
+    assert lib.cyl_batch_destroy(None) == 1
 
 
 def test_adi_parameter_validation():
