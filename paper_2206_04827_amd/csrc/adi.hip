@@ -293,14 +293,15 @@ __device__ __forceinline__ void lds_barrier() {
 
 // r-pass, rows [0, t) of column k (LU records).  pre: W rows t, t+1, t+2 of
 // this column, read before any thread overwrote them.  Returns g_{t-2}, g_{t-1}.
-template <int LD>
+template <int LD, int G>
 __device__ __forceinline__ void rs_top_fwd(double* __restrict__ S, int t, int k,
                                            const double* __restrict__ RC,
                                            const double* __restrict__ Ecol, double vmu,
                                            const double pre[3], double* gt2, double* gt1) {
     const double2* E2 = reinterpret_cast<const double2*>(Ecol);
+    static_assert(G >= 4 && G % 2 == 0, "row group");
     double* Sk = S + k;
-    double wv[14];                 // rows i0-2 .. i0+11 of W
+    double wv[G + 6];              // rows i0-2 .. i0+G+3 of W
     wv[0] = 0.0; wv[1] = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) wv[2 + q] = Sk[q * LD];
@@ -322,11 +323,11 @@ __device__ __forceinline__ void rs_top_fwd(double* __restrict__ S, int t, int k,
             }
         if (i0 + G < t) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) wv[6 + q] = Sg[(4 + q) * LD];
+            for (int q = 0; q < G; ++q) wv[6 + q] = Sg[(4 + q) * LD];
         } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) wv[6 + q] = Sg[(4 + q) * LD];
-            wv[10] = pre[0]; wv[11] = pre[1]; wv[12] = pre[2]; wv[13] = 0.0;
+            for (int q = 0; q < G - 4; ++q) wv[6 + q] = Sg[(4 + q) * LD];
+            wv[G + 2] = pre[0]; wv[G + 3] = pre[1]; wv[G + 4] = pre[2]; wv[G + 5] = 0.0;
         }
         double2 enn[G / 2];
 #pragma unroll
@@ -348,7 +349,7 @@ __device__ __forceinline__ void rs_top_fwd(double* __restrict__ S, int t, int k,
             g1 = g;
         }
 #pragma unroll
-        for (int q = 0; q < 6; ++q) wv[q] = wv[8 + q];
+        for (int q = 0; q < 6; ++q) wv[q] = wv[G + q];
 #pragma unroll
         for (int q = 0; q < G / 2; ++q) { eb[q] = en[q]; en[q] = enn[q]; }
     }
@@ -357,7 +358,7 @@ __device__ __forceinline__ void rs_top_fwd(double* __restrict__ S, int t, int k,
 }
 
 // r-pass back substitution on rows t-1 .. 0, starting from x_t, x_{t+1}, x_{t+2}.
-template <int LD>
+template <int LD, int G>
 __device__ __forceinline__ void rs_top_bwd(double* __restrict__ S, int t, int k,
                                            const double* __restrict__ RC, double z1, double z2,
                                            double z3) {
@@ -396,7 +397,7 @@ __device__ __forceinline__ void rs_top_bwd(double* __restrict__ S, int t, int k,
 
 // r-pass, rows mp-1 .. t of column k (UL records, upwards).  preb: W rows
 // t-2, t-1 of this column.  Returns g'_t, g'_{t+1}, g'_{t+2}.
-template <int LD>
+template <int LD, int G>
 __device__ __forceinline__ void rs_bot_fwd(double* __restrict__ S, int mp, int t, int k,
                                            const double* __restrict__ RC,
                                            const double* __restrict__ Ecol, double vmu,
@@ -404,7 +405,8 @@ __device__ __forceinline__ void rs_bot_fwd(double* __restrict__ S, int mp, int t
                                            double* g2) {
     const double2* E2 = reinterpret_cast<const double2*>(Ecol);
     double* Sk = S + k;
-    double up[3] = {0.0, 0.0, 0.0};        // old W rows i0+8 .. i0+10
+    static_assert(G >= 4 && G % 2 == 0, "row group");
+    double up[3] = {0.0, 0.0, 0.0};        // old W rows i0+G .. i0+G+2
     double gp1 = 0.0, gp2 = 0.0, gp3 = 0.0;  // g'_{i+1}, g'_{i+2}, g'_{i+3}
     double2 eb[G / 2], en[G / 2];
 #pragma unroll
@@ -421,7 +423,7 @@ __device__ __forceinline__ void rs_bot_fwd(double* __restrict__ S, int mp, int t
                 c[q][2 * s] = v.x;
                 c[q][2 * s + 1] = v.y;
             }
-        double w[13];                      // rows i0-2 .. i0+10 of W
+        double w[G + 5];                   // rows i0-2 .. i0+G+2 of W
         if (i0 > t) {
             w[0] = Sg[-2 * LD];
             w[1] = Sg[-LD];
@@ -431,7 +433,7 @@ __device__ __forceinline__ void rs_bot_fwd(double* __restrict__ S, int mp, int t
         }
 #pragma unroll
         for (int q = 0; q < G; ++q) w[2 + q] = Sg[q * LD];
-        w[10] = up[0]; w[11] = up[1]; w[12] = up[2];
+        w[G + 2] = up[0]; w[G + 3] = up[1]; w[G + 4] = up[2];
         double2 enn[G / 2];
         if (i0 >= 2 * G) {
 #pragma unroll
@@ -465,7 +467,7 @@ __device__ __forceinline__ void rs_bot_fwd(double* __restrict__ S, int mp, int t
 }
 
 // r-pass forward substitution on rows t .. mp-1, starting from x_{t-1}, x_{t-2}.
-template <int LD>
+template <int LD, int G>
 __device__ __forceinline__ void rs_bot_bwd(double* __restrict__ S, int mp, int t, int k,
                                            const double* __restrict__ RC, double xm1, double xm2) {
     double* Sk = S + k;
@@ -499,6 +501,7 @@ __device__ __forceinline__ void rs_bot_bwd(double* __restrict__ S, int mp, int t
 }
 
 // z-pass, columns [0, t) of one row (LU records).  Returns g_{t-1}.
+template <int G>
 __device__ __forceinline__ double zs_top_fwd(double* __restrict__ row, int t,
                                              const double* __restrict__ ZC) {
     double zb[G];
@@ -527,7 +530,7 @@ __device__ __forceinline__ double zs_top_fwd(double* __restrict__ row, int t,
 // z-pass back substitution on columns t-1 .. 0 from x_t, x_{t+1}; unless this
 // is the last iteration, each x is replaced by w = x (u' B + D) on the fly
 // (columns < t only).
-template <bool kLast>
+template <bool kLast, int G>
 __device__ __forceinline__ void zs_top_bwd(double* __restrict__ row, int t,
                                            const double* __restrict__ ZC, double x1, double x2) {
     double gb[G];
@@ -573,6 +576,7 @@ __device__ __forceinline__ void zs_top_bwd(double* __restrict__ row, int t,
 
 // z-pass, columns np-1 .. t of one row (UL records, leftwards).  Returns
 // g'_t, g'_{t+1}.
+template <int G>
 __device__ __forceinline__ void zs_bot_fwd(double* __restrict__ row, int np, int t,
                                            const double* __restrict__ ZC, double* g0,
                                            double* g1) {
@@ -608,7 +612,7 @@ __device__ __forceinline__ void zs_bot_fwd(double* __restrict__ row, int np, int
 // z-pass forward substitution on columns t .. np-1 from x_{t-1}; unless this
 // is the last iteration, w_{k-2} = x (u' B + D) at column k-2 >= t is written
 // as soon as x_k is known, and the last two columns after the loop.
-template <bool kLast>
+template <bool kLast, int G>
 __device__ __forceinline__ void zs_bot_bwd(double* __restrict__ row, int np, int t,
                                            const double* __restrict__ ZC, double xm1) {
     double gb[G];
@@ -658,8 +662,17 @@ __device__ __forceinline__ void zs_bot_bwd(double* __restrict__ row, int np, int
 // One workgroup (2 L threads) per parity block, all J iterations in LDS.
 // LDS: state (mp rows of LD), r records (+ coupling), z records (+ coupling),
 // exchange area (5 x L).
-template <int LD>
-__device__ __forceinline__ void adi_block_split(double* sm, const BlockDesc& bd,
+// kGS: the block state lives in global memory (gS, mp rows of LD; blocks too
+// large for LDS), records and the exchange area stay in LDS, and the barriers
+// between the halves also wait for the state's vector-memory traffic.
+template <bool kGS>
+__device__ __forceinline__ void half_barrier() {
+    if (kGS) __syncthreads();
+    else lds_barrier();
+}
+
+template <int LD, bool kGS>
+__device__ __forceinline__ void adi_block_split(double* sm, double* gS, const BlockDesc& bd,
                                                 const double* __restrict__ E, double* X,
                                                 const double* __restrict__ rtab,
                                                 const double* __restrict__ ztab,
@@ -668,9 +681,12 @@ __device__ __forceinline__ void adi_block_split(double* sm, const BlockDesc& bd,
     const int tid = threadIdx.x, nt = blockDim.x, L = nt >> 1;
     const int line = tid % L;
     const bool top = tid < L;
-    double* S = sm;
+    // rows per software-pipelined group: 4 when the state is in global memory
+    // (512-thread workgroups leave 256 registers per thread)
+    constexpr int GG = kGS ? 4 : G;
+    double* S = kGS ? gS : sm;
     const int nr = (mp + kRCouple) * kRRec, nz = (np + kZCouple) * kZRec;
-    double* RCs = S + mp * LD;
+    double* RCs = kGS ? sm : S + mp * LD;
     double* ZCs = RCs + lds_chunks(nr);
     double* XC = ZCs + lds_chunks(nz);
     for (int idx = tid; idx < mp * LD; idx += nt) S[idx] = 0.0;
@@ -692,22 +708,22 @@ __device__ __forceinline__ void adi_block_split(double* sm, const BlockDesc& bd,
                 for (int s = 0; s < 2; ++s) pre[s] = S[(tr - 2 + s) * LD + line];
             }
         }
-        lds_barrier();
+        half_barrier<kGS>();
         if (line < ne) {
             if (top) {
                 double a, b;
-                rs_top_fwd<LD>(S, tr, line, RCs, Ecol, vm, pre, &a, &b);
+                rs_top_fwd<LD, GG>(S, tr, line, RCs, Ecol, vm, pre, &a, &b);
                 XC[line] = a;
                 XC[L + line] = b;
             } else {
                 double a, b, c;
-                rs_bot_fwd<LD>(S, mp, tr, line, RCs, Ecol, vm, pre, &a, &b, &c);
+                rs_bot_fwd<LD, GG>(S, mp, tr, line, RCs, Ecol, vm, pre, &a, &b, &c);
                 XC[2 * L + line] = a;
                 XC[3 * L + line] = b;
                 XC[4 * L + line] = c;
             }
         }
-        lds_barrier();
+        half_barrier<kGS>();
         if (line < ne) {
             double v[5], y[5];
 #pragma unroll
@@ -717,8 +733,8 @@ __device__ __forceinline__ void adi_block_split(double* sm, const BlockDesc& bd,
             for (int r = 0; r < 5; ++r)
                 y[r] = K5[5 * r] * v[0] + K5[5 * r + 1] * v[1] + K5[5 * r + 2] * v[2] +
                        K5[5 * r + 3] * v[3] + K5[5 * r + 4] * v[4];
-            if (top) rs_top_bwd<LD>(S, tr, line, RCs, y[2], y[3], y[4]);
-            else rs_bot_bwd<LD>(S, mp, tr, line, RCs, y[1], y[0]);
+            if (top) rs_top_bwd<LD, GG>(S, tr, line, RCs, y[2], y[3], y[4]);
+            else rs_bot_bwd<LD, GG>(S, mp, tr, line, RCs, y[1], y[0]);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
@@ -728,15 +744,15 @@ __device__ __forceinline__ void adi_block_split(double* sm, const BlockDesc& bd,
         double* row = S + line * LD;
         if (line < me) {
             if (top) {
-                XC[line] = zs_top_fwd(row, tz, ZCs);
+                XC[line] = zs_top_fwd<GG>(row, tz, ZCs);
             } else {
                 double a, b;
-                zs_bot_fwd(row, np, tz, ZCs, &a, &b);
+                zs_bot_fwd<GG>(row, np, tz, ZCs, &a, &b);
                 XC[L + line] = a;
                 XC[2 * L + line] = b;
             }
         }
-        lds_barrier();
+        half_barrier<kGS>();
         if (line < me) {
             const double v0 = XC[line], v1 = XC[L + line], v2 = XC[2 * L + line];
             const double* K3 = ZCs + np * kZRec;
@@ -744,11 +760,11 @@ __device__ __forceinline__ void adi_block_split(double* sm, const BlockDesc& bd,
             const double y1 = K3[3] * v0 + K3[4] * v1 + K3[5] * v2;
             const double y2 = K3[6] * v0 + K3[7] * v1 + K3[8] * v2;
             if (top) {
-                if (more) zs_top_bwd<false>(row, tz, ZCs, y1, y2);
-                else zs_top_bwd<true>(row, tz, ZCs, y1, y2);
+                if (more) zs_top_bwd<false, GG>(row, tz, ZCs, y1, y2);
+                else zs_top_bwd<true, GG>(row, tz, ZCs, y1, y2);
             } else {
-                if (more) zs_bot_bwd<false>(row, np, tz, ZCs, y0);
-                else zs_bot_bwd<true>(row, np, tz, ZCs, y0);
+                if (more) zs_bot_bwd<false, GG>(row, np, tz, ZCs, y0);
+                else zs_bot_bwd<true, GG>(row, np, tz, ZCs, y0);
             }
         }
         __builtin_amdgcn_s_waitcnt(0);
@@ -774,7 +790,27 @@ void k_adi_split(const BlockDesc* __restrict__ blocks, const double* __restrict_
         const AdiPtrs q = pp[bd.prob];
         E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
     }
-    adi_block_split<NP + 1>(sm, bd, E, X, rtab, ztab, vmu, accumulate);
+    adi_block_split<NP + 1, false>(sm, nullptr, bd, E, X, rtab, ztab, vmu, accumulate);
+}
+
+// Blocks too large for LDS (n up to 514): split sweeps with the state in
+// global memory, slot blockIdx.x of `state` (state_stride doubles each).
+template <int NP>
+__global__ __launch_bounds__(512) void k_adi_split_gs(const BlockDesc* __restrict__ blocks,
+                                                      const double* __restrict__ E, double* X,
+                                                      double* state, int64_t state_stride,
+                                                      const double* __restrict__ rtab,
+                                                      const double* __restrict__ ztab,
+                                                      const double* __restrict__ vmu, int accumulate,
+                                                      const AdiPtrs* __restrict__ pp) {
+    extern __shared__ double sm[];
+    const BlockDesc bd = blocks[blockIdx.x];
+    if (pp != nullptr) {
+        const AdiPtrs q = pp[bd.prob];
+        E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
+    }
+    adi_block_split<NP + 1, true>(sm, state + static_cast<int64_t>(blockIdx.x) * state_stride, bd, E, X, rtab,
+                                  ztab, vmu, accumulate);
 }
 
 // ---------------------------------------------------------------------------
@@ -1231,6 +1267,16 @@ hipError_t launch_split(const BlockDesc* blocks, int nblocks, int threads, const
 }
 
 template <int NP>
+hipError_t launch_split_gs(const BlockDesc* blocks, int nblocks, int threads, const double* E, double* X,
+                           double* state, int64_t state_stride, const double* rtab, const double* ztab,
+                           const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
+                           const AdiPtrs* pp) {
+    hipLaunchKernelGGL(k_adi_split_gs<NP>, dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X, state,
+                       state_stride, rtab, ztab, vmu, accumulate ? 1 : 0, pp);
+    return hipGetLastError();
+}
+
+template <int NP>
 hipError_t set_split_limit(size_t bytes) {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_split<NP>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
@@ -1273,6 +1319,33 @@ hipError_t launch_adi_split(const BlockDesc* blocks, int nblocks, int threads, i
     switch (np0) {
 #define CYL_CASE(v) case v: return launch_split<v>(blocks, nblocks, threads, E, X, rtab, ztab, vmu, accumulate, lds_bytes, s, pp);
         CYL_NP_CASES(CYL_CASE)
+#undef CYL_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+#define CYL_NP_GS_CASES(X) X(136) X(144) X(152) X(160) X(168) X(176) X(184) X(192) X(200) X(208) \
+    X(216) X(224) X(232) X(240) X(248) X(256)
+
+size_t adi_split_gs_lds_bytes(int mp0, int np0, int lines) {
+    auto chunks = [](int x) { return static_cast<size_t>((x + 127) / 128 * 128); };
+    const size_t doubles = chunks((mp0 + kRCouple) * kRRec) + chunks((np0 + kZCouple) * kZRec) +
+                           5 * static_cast<size_t>(lines);
+    return doubles * sizeof(double);
+}
+
+int64_t adi_split_gs_state_stride(int mp0, int np0) {
+    return static_cast<int64_t>(mp0) * (np0 + 1) + 64;
+}
+
+hipError_t launch_adi_split_gs(const BlockDesc* blocks, int nblocks, int threads, int np0,
+                               const double* E, double* X, double* state, int64_t state_stride,
+                               const double* rtab, const double* ztab, const double* vmu,
+                               bool accumulate, size_t lds_bytes, hipStream_t s, const AdiPtrs* pp) {
+    if (threads < 128 || threads > 512 || threads % 128 != 0) return hipErrorInvalidValue;
+    switch (np0) {
+#define CYL_CASE(v) case v: return launch_split_gs<v>(blocks, nblocks, threads, E, X, state, state_stride, rtab, ztab, vmu, accumulate, lds_bytes, s, pp);
+        CYL_NP_GS_CASES(CYL_CASE)
 #undef CYL_CASE
         default: return hipErrorInvalidValue;
     }

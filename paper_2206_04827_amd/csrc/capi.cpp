@@ -134,6 +134,7 @@ struct cyl_plan_s {
     DevMem planesA, planesB, E, X, R, state, acc;
     bool use_lds = false;
     bool adi_split = false;        // split-sweep kernel (two threads per line)
+    bool split_gs = false;         //   with the block state in global memory
     int64_t state_stride = 0;
     int adi_threads = 64;
     size_t lds_bytes = 0;
@@ -462,7 +463,13 @@ void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X) {
             rhs = pl->R.as<double>();
         }
         Scope sc(pl, PH_ADI);
-        if (pl->adi_split)
+        if (pl->adi_split && pl->split_gs)
+            hip_check(launch_adi_split_gs(s->blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
+                                          pl->state.as<double>(), pl->state_stride, s->rtab.as<double>(),
+                                          s->ztab.as<double>(), s->vmu.as<double>(), pass > 0, pl->lds_bytes,
+                                          pl->stream),
+                      "adi");
+        else if (pl->adi_split)
             hip_check(launch_adi_split(s->blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
                                        s->rtab.as<double>(), s->ztab.as<double>(), s->vmu.as<double>(),
                                        pass > 0, pl->lds_bytes, pl->stream),
@@ -619,6 +626,17 @@ void build_plan(cyl_plan_t pl) {
             pl->lds_bytes = sb;
             pl->use_lds = true;
         }
+    } else if (env_int("CYLSPEC_ADI_SPLIT", 1) != 0 && mode == 0 && g.np[0] > 128 && g.np[0] <= 256 &&
+               g.mp[0] <= 256 && adi_split_fits(std::min(g.me[0], g.me[1]), std::min(g.ne[0], g.ne[1]))) {
+        // blocks too large for LDS: split sweeps with the state in global memory
+        const int lines = ((std::max(g.me[0], g.ne[0]) + 63) / 64) * 64;
+        pl->adi_split = true;
+        pl->split_gs = true;
+        pl->adi_threads = 2 * lines;
+        pl->lds_bytes = adi_split_gs_lds_bytes(g.mp[0], g.np[0], lines);
+        pl->state_stride = adi_split_gs_state_stride(g.mp[0], g.np[0]);
+        pl->state.alloc(static_cast<size_t>(4 * g.nplanes) * pl->state_stride * sizeof(double));
+        pl->use_lds = true;        // no HBM-state one-thread kernel
     }
     if (!pl->use_lds) {
         pl->adi_threads = std::min(512, pl->adi_threads);
@@ -628,7 +646,8 @@ void build_plan(cyl_plan_t pl) {
         std::fprintf(stderr, "[cylspec] plan %dx%dx%d: blocks me=(%d,%d) ne=(%d,%d), ADI %s, %d threads, "
                              "LDS %zu of %d bytes, DFT Nb r/z/theta = %d/%d/%d\n",
                      m, n, p, g.me[0], g.me[1], g.ne[0], g.ne[1],
-                     pl->adi_split ? "LDS-resident split" : pl->use_lds ? "LDS-resident" : "HBM-resident",
+                     pl->split_gs ? "split, global state" : pl->adi_split ? "LDS-resident split"
+                                                           : pl->use_lds ? "LDS-resident" : "HBM-resident",
                      pl->adi_threads, pl->lds_bytes, max_lds, pl->dr.t.Nb, pl->dz.t.Nb, pl->dth.t.Nb);
 }
 
@@ -654,7 +673,9 @@ void heat_step_bdf1(cyl_heat_t h, const double* Pin, double* X, double* Pout) {
 // ---------------------------------------------------------------------------
 // batched heat stepping
 // ---------------------------------------------------------------------------
-int adi_kind(const cyl_plan_s* pl) { return pl->adi_split ? 0 : (pl->use_lds ? 1 : 2); }
+int adi_kind(const cyl_plan_s* pl) {
+    return pl->split_gs ? 3 : pl->adi_split ? 0 : (pl->use_lds ? 1 : 2);
+}
 
 struct BlockRef {
     BlockDesc b;
@@ -696,6 +717,13 @@ std::vector<BatchLaunch> build_launches(const std::vector<BlockRef>& refs, int g
         } else if (l.kind == 1) {
             l.lds = (static_cast<size_t>(mp + 4) * (l.np + 1) + chunks(kRRec * mp) + chunks(kZRec * l.np)) * sizeof(double);
             if (l.lds > 65536) hip_check(adi_set_lds_limit(l.np, l.lds), "LDS limit");
+        } else if (l.kind == 3) {
+            // the kernel's row stride is the group's np + 1: size every slot for
+            // the group's largest mp at that stride
+            l.lds = adi_split_gs_lds_bytes(mp, l.np, l.threads / 2);
+            l.state_stride = adi_split_gs_state_stride(mp, l.np);
+            l.state = std::make_unique<DevMem>();
+            l.state->alloc(static_cast<size_t>(l.nblocks) * l.state_stride * sizeof(double));
         } else {
             l.state = std::make_unique<DevMem>();
             l.state->alloc(static_cast<size_t>(l.nblocks) * l.state_stride * sizeof(double));
@@ -716,6 +744,10 @@ void run_adi_launches(hipStream_t st, const std::vector<BatchLaunch>& ls, const 
         if (l.kind == 0)
             hip_check(launch_adi_split(bl, l.nblocks, l.threads, l.np, nullptr, nullptr, nullptr, nullptr, nullptr,
                                        acc, l.lds, st, pp), "batched adi");
+        else if (l.kind == 3)
+            hip_check(launch_adi_split_gs(bl, l.nblocks, l.threads, l.np, nullptr, nullptr, l.state->as<double>(),
+                                          l.state_stride, nullptr, nullptr, nullptr, acc, l.lds, st, pp),
+                      "batched adi");
         else
             hip_check(launch_adi(bl, l.nblocks, l.threads, l.np, nullptr, nullptr,
                                  l.state ? l.state->as<double>() : nullptr, l.state_stride, nullptr, nullptr,
@@ -828,15 +860,16 @@ void batch_build(cyl_batch_s* B, int flags) {
                           static_cast<int64_t>(g.me[0] + g.me[1]) * 12, g.me[0], g.ne[0]};
         const int kind = adi_kind(pl);
         const int lines = ((std::max(g.me[0], g.ne[0]) + 63) / 64) * 64;
-        const int threads = kind == 0 ? 2 * lines : std::min(512, lines);
+        const int threads = (kind == 0 || kind == 3) ? 2 * lines : std::min(512, lines);
+        const int64_t sstride = kind == 3 ? adi_split_gs_state_stride(g.mp[0], g.np[0])
+                                          : static_cast<int64_t>(g.mp[0] + 4) * (g.np[0] + 1);
         key << kind << ':' << g.np[0] << ':' << g.mp[0] << ':' << s->hblocks.size() << ':' << s->passes << ';';
         for (const BlockDesc& b0 : s->hblocks) {
             BlockDesc b = b0;
             b.prob = q;
             const int bi = static_cast<int>(all.size());
             all.push_back(b);
-            BlockRef r{b, static_cast<double>(b.J) * b.me * b.ne, kind, threads, g.np[0], g.mp[0],
-                       static_cast<int64_t>(g.mp[0] + 4) * (g.np[0] + 1)};
+            BlockRef r{b, static_cast<double>(b.J) * b.me * b.ne, kind, threads, g.np[0], g.mp[0], sstride};
             refs1.push_back(r);
             if (s->passes == 2) refs2.push_back(r);
             for (int ti = 0; ti * 32 < b.me; ++ti)

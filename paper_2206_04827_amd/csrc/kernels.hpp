@@ -119,6 +119,16 @@ hipError_t launch_adi_split(const BlockDesc* blocks, int nblocks, int threads, i
                             const AdiPtrs* pp = nullptr);
 // LDS bytes of the split kernel for padded block sizes mp0 x np0.
 size_t adi_split_lds_bytes(int mp0, int np0);
+// Split sweeps with the block state in global memory (np0 in 136..256, a
+// multiple of 8; threads = 2 lines <= 512): state slot blockIdx.x of `state`,
+// state_stride = adi_split_gs_state_stride(mp0, np0) doubles (or more).
+hipError_t launch_adi_split_gs(const BlockDesc* blocks, int nblocks, int threads, int np0,
+                               const double* E, double* X, double* state, int64_t state_stride,
+                               const double* rtab, const double* ztab, const double* vmu,
+                               bool accumulate, size_t lds_bytes, hipStream_t s,
+                               const AdiPtrs* pp = nullptr);
+size_t adi_split_gs_lds_bytes(int mp0, int np0, int lines);
+int64_t adi_split_gs_state_stride(int mp0, int np0);
 
 // Raise the dynamic-LDS limit of the LDS-resident ADI kernels for width np0.
 hipError_t adi_set_lds_limit(int np0, size_t bytes);

@@ -112,6 +112,28 @@ def test_variants_match(env):
     assert_close(u, pb.poisson(f), TOL, str(env))
 
 
+@pytest.mark.parametrize("m,n,p", [(290, 270, 3), (400, 350, 2)])
+def test_large_block_sizes_full_field(m, n, p):
+    """Parity blocks too large for LDS (split sweeps with the block state in
+    global memory, 384 and 512 threads): full field against the oracle, and
+    against the one-thread-per-line HBM kernel."""
+    need_gpu()
+    banner("poisson large blocks m=%d n=%d p=%d" % (m, n, p))
+    f = smooth_values(m, n, p, S + 31 + m)
+    u = _solve_values(m, n, p, f)
+    assert_close(u, pb.poisson(f), TOL, "split, global state")
+    old = os.environ.get("CYLSPEC_ADI_SPLIT")
+    os.environ["CYLSPEC_ADI_SPLIT"] = "0"
+    try:
+        v = _solve_values(m, n, p, f)
+    finally:
+        if old is None:
+            os.environ.pop("CYLSPEC_ADI_SPLIT")
+        else:
+            os.environ["CYLSPEC_ADI_SPLIT"] = old
+    assert_close(u, v, TOL, "split vs one-thread kernel")
+
+
 def test_non_finite_input_reports_not_converged():
     need_gpu()
     m, n, p = 10, 10, 4
