@@ -88,15 +88,20 @@ void upload(DevMem& m, const std::vector<T>& v) {
     if (!v.empty()) hip_check(hipMemcpy(m.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
 }
 
+int env_int(const char* name, int dflt);
+static_assert(kMaxDftPasses == kMaxRadixPasses, "radix plan fits the device view");
+
 struct DftOwned {
     DftTables t;
     DevMem tw, chirp, bhat;
     DftDev view{};
     void build(int L) {
-        t = build_dft_tables(L);
+        t = build_dft_tables(L, env_int("CYLSPEC_DFT_MIXED", 1) != 0);
         upload(tw, t.tw);
         if (t.bluestein) { upload(chirp, t.chirp); upload(bhat, t.bhat); }
-        view.L = t.L; view.Nb = t.Nb; view.log2Nb = t.log2Nb; view.bluestein = t.bluestein ? 1 : 0;
+        view.L = t.L; view.Nb = t.Nb; view.tpl = t.tpl; view.bluestein = t.bluestein ? 1 : 0;
+        view.nrad = static_cast<int>(t.radices.size());
+        for (int i = 0; i < kMaxDftPasses; ++i) view.rad[i] = i < view.nrad ? t.radices[i] : 0;
         view.tw = tw.as<double2>();
         view.chirp = t.bluestein ? chirp.as<double2>() : nullptr;
         view.bhat = t.bluestein ? bhat.as<double2>() : nullptr;

@@ -7,9 +7,13 @@
 namespace cyl {
 
 // Device view of one DFT length (see DftTables): complex length L computed as
-// a power-of-two FFT of length Nb, directly (L == Nb) or by Bluestein.
+// a mixed-radix FFT of length Nb, directly (L == Nb) or by Bluestein
+// (power-of-two Nb).  Pass p of the Stockham FFT has radix rad[p].
+constexpr int kMaxDftPasses = 12;
 struct DftDev {
-    int L, Nb, log2Nb, bluestein;
+    int L, Nb, tpl, bluestein;     // tpl: threads per line
+    int nrad;
+    int rad[kMaxDftPasses];
     const double2* tw;      // Nb: per-pass twiddles of the Stockham FFT
     const double2* chirp;   // L   (Bluestein only)
     const double2* bhat;    // Nb  (Bluestein only)

@@ -736,27 +736,69 @@ void host_fft(std::vector<cld>& x) {      // forward, sign -1, length power of t
 
 }  // namespace
 
-DftTables build_dft_tables(int L) {
+bool dft_radix_plan(int N, std::vector<int>* radices) {
+    radices->clear();
+    if (N < 1) return false;
+    int n = N, p2 = 1;
+    while (n % 2 == 0) { n /= 2; p2 *= 2; }
+    int big = 0, nbig = 0;                 // the odd prime factor 7, 11, 13 or 17
+    for (int q : {17, 13, 11, 7})
+        while (n % q == 0) { n /= q; big = q; ++nbig; }
+    int c3 = 0, c5 = 0;
+    while (n % 3 == 0) { n /= 3; ++c3; }
+    while (n % 5 == 0) { n /= 5; ++c5; }
+    // the kernels run such a factor only as the first pass (no twiddles)
+    if (n != 1 || nbig > 1) return false;
+    if (big) radices->push_back(big);
+    for (int Ls = 1; Ls < p2;) {
+        const int rem = p2 / Ls;
+        const int R = rem >= 16 ? 16 : rem;
+        radices->push_back(R);
+        Ls *= R;
+    }
+    for (; c3 > 0 && c5 > 0; --c3, --c5) radices->push_back(15);
+    for (; c5 > 0; --c5) radices->push_back(5);
+    for (; c3 > 0; --c3) radices->push_back(3);
+    return static_cast<int>(radices->size()) <= kMaxRadixPasses;
+}
+
+int dft_threads_per_line(int N, const std::vector<int>& radices) {
+    int lo = std::max(1, (N + 15) / 16);
+    for (int R : radices)
+        if (R >= 11) lo = std::max(lo, N / R);      // one butterfly per thread
+    int best = lo;
+    long long best_cost = -1;
+    for (int T = lo; T <= std::max(lo, std::min(N, 2 * lo)); ++T) {
+        long long c = 0;
+        for (int R : radices) c += static_cast<long long>((N / R + T - 1) / T) * R;
+        c *= T;
+        if (best_cost < 0 || c < best_cost) { best_cost = c; best = T; }
+    }
+    return best;
+}
+
+DftTables build_dft_tables(int L, bool mixed) {
     DftTables t;
     t.L = L;
     const long double pi = 3.141592653589793238462643383279502884L;
     const bool pow2 = (L & (L - 1)) == 0;
-    t.bluestein = !pow2;
+    std::vector<int> rad;
+    t.bluestein = !(pow2 || (mixed && dft_radix_plan(L, &rad)));
     int Nb = 1;
-    if (pow2) Nb = L;
+    if (!t.bluestein) Nb = L;
     else while (Nb < 2 * L - 1) Nb <<= 1;
     t.Nb = Nb;
-    while ((1 << t.log2Nb) < Nb) ++t.log2Nb;
-    // Per-pass twiddles of the radix-16/8/4/2 Stockham FFT, in pass order:
-    // for the pass of radix R on sub-transforms of length Ls, entries
+    if (!dft_radix_plan(Nb, &t.radices)) throw std::runtime_error("DFT radix plan");
+    t.tpl = dft_threads_per_line(Nb, t.radices);
+    // Per-pass twiddles of the Stockham FFT, in pass order: for the pass of
+    // radix R on sub-transforms of length Ls, entries
     // [k (R-1) + q - 1] = exp(-2 pi i k q / (R Ls)), k < Ls, 1 <= q < R
-    // (N - 1 entries in total; the table is padded to Nb).
+    // (Nb - 1 entries in total; the table is padded to Nb).
     t.tw.assign(2 * static_cast<size_t>(Nb), 0.0);
     {
         size_t off = 0;
-        for (int Ls = 1; Ls < Nb;) {
-            const int rem = Nb / Ls;
-            const int R = rem >= 16 ? 16 : rem;
+        int Ls = 1;
+        for (int R : t.radices) {
             for (int k = 0; k < Ls; ++k)
                 for (int q = 1; q < R; ++q) {
                     const long double ang = -2.0L * pi * static_cast<long double>(k) * q /

@@ -58,15 +58,25 @@ void adi_shifts(double a, double b, double c, double d, int J, double* u, double
 double jacobi_dn_frac(double t, double kp);   // dn(t K(k), k), 0 <= t <= 1
 double ellip_K_from_kp(double kp);
 
-// Per-length DFT tables (complex length L; power-of-two FFT length Nb).
+constexpr int kMaxRadixPasses = 12;
+// Per-length DFT tables (complex length L; FFT length Nb = L when L factors
+// into the supported radices, else the power of two >= 2L - 1 of Bluestein).
 struct DftTables {
-    int L = 0, Nb = 0, log2Nb = 0;
+    int L = 0, Nb = 0, tpl = 1;     // tpl: threads per line in the kernels
     bool bluestein = false;
+    std::vector<int> radices;   // Stockham pass radices, first pass first
     std::vector<double> tw;     // 2*Nb: per-pass FFT twiddles (see build_dft_tables)
     std::vector<double> chirp;  // 2*L : exp(-i pi n^2 / L)
     std::vector<double> bhat;   // 2*Nb: FFT of the Bluestein filter, times 1/Nb
 };
-DftTables build_dft_tables(int L);
+DftTables build_dft_tables(int L, bool mixed = true);
+// Radix plan of a length-N FFT: an odd prime factor 7, 11, 13 or 17 first
+// (at most one), 16/8/4/2 for the power-of-two part, then 15, 5, 3; false
+// for any other N.
+bool dft_radix_plan(int N, std::vector<int>* radices);
+// Threads per line for a length-N FFT with the given passes: at least N / 16
+// (and N / R for radices R >= 11), balancing the butterflies of every pass.
+int dft_threads_per_line(int N, const std::vector<int>& radices);
 
 // Record layouts of the ADI coefficient tables (doubles per row).
 constexpr int kRRec = 12;   // r-pass: (vC - A) row[6], L[2], dinv, dinv*U[3]

@@ -6,10 +6,11 @@
 // r, z : DCT-I of length M + 1 through a length-M DFT of the folded line
 //        (see k_dct); complex lines carry the DCT of their real and
 //        imaginary parts at once.
-// Every DFT is a power-of-two Stockham FFT in LDS made of radix-16/8/4/2
-// passes whose butterflies run in registers; the twiddle table is staged in
-// LDS once per workgroup.  Lengths that are not powers of two go through
-// Bluestein's chirp-z identity with a power-of-two convolution.
+// Every DFT is a mixed-radix Stockham FFT in LDS whose butterflies run in
+// registers (radices 16, 8, 4, 2 and 3, 5, 7, 11, 13, 15, 17); the twiddle
+// table is staged in LDS once per workgroup.  Lengths with another prime
+// factor go through Bluestein's chirp-z identity with a power-of-two
+// convolution.
 #include "kernels.hpp"
 
 namespace cyl {
@@ -102,6 +103,112 @@ __device__ __forceinline__ void dft_reg<16>(double2* x) {
     }
 }
 
+// (cos, sin)(2 pi e / R) for 0 <= e < R (0 <= e <= 8 for R = 15), correctly
+// rounded; e is a compile-time constant wherever these are called.
+template <int R>
+__device__ __forceinline__ double2 root(int e);
+
+#define CYL_ROOTS(R, ...)                                                         \
+    template <>                                                                   \
+    __device__ __forceinline__ double2 root<R>(int e) {                           \
+        constexpr double cs[2][R / 2 + 2] = __VA_ARGS__;                          \
+        return 2 * e <= R ? make_double2(cs[0][e], cs[1][e])                      \
+                          : make_double2(cs[0][R - e], -cs[1][R - e]);            \
+    }
+CYL_ROOTS(3, {{1.0, -0.5, 0.0}, {0.0, 0.8660254037844386, 0.0}})
+CYL_ROOTS(5, {{1.0, 0.30901699437494745, -0.8090169943749475, 0.0},
+              {0.0, 0.9510565162951535, 0.5877852522924731, 0.0}})
+CYL_ROOTS(7, {{1.0, 0.6234898018587335, -0.2225209339563144, -0.9009688679024191, 0.0},
+              {0.0, 0.7818314824680298, 0.9749279121818236, 0.4338837391175581, 0.0}})
+CYL_ROOTS(11, {{1.0, 0.8412535328311812, 0.41541501300188644, -0.14231483827328514,
+                -0.6548607339452851, -0.9594929736144974, 0.0},
+               {0.0, 0.5406408174555976, 0.9096319953545183, 0.9898214418809327,
+                0.7557495743542583, 0.28173255684142967, 0.0}})
+CYL_ROOTS(13, {{1.0, 0.8854560256532099, 0.5680647467311558, 0.12053668025532305,
+                -0.3546048870425356, -0.7485107481711011, -0.970941817426052, 0.0},
+               {0.0, 0.46472317204376856, 0.8229838658936564, 0.992708874098054,
+                0.9350162426854148, 0.6631226582407952, 0.23931566428755777, 0.0}})
+CYL_ROOTS(15, {{1.0, 0.9135454576426009, 0.6691306063588582, 0.30901699437494745,
+                -0.10452846326765347, -0.5, -0.8090169943749475, -0.9781476007338057,
+                -0.9781476007338057},
+               {0.0, 0.4067366430758002, 0.7431448254773942, 0.9510565162951535,
+                0.9945218953682733, 0.8660254037844386, 0.5877852522924731,
+                0.20791169081775934, -0.20791169081775934}})
+CYL_ROOTS(17, {{1.0, 0.9324722294043558, 0.7390089172206591, 0.44573835577653825,
+                0.092268359463302, -0.2736629900720829, -0.6026346363792564,
+                -0.8502171357296141, -0.9829730996839018, 0.0},
+               {0.0, 0.3612416661871529, 0.6736956436465572, 0.8951632913550623,
+                0.9957341762950345, 0.961825643172819, 0.7980172272802395,
+                0.5264321628773558, 0.18374951781657034, 0.0}})
+#undef CYL_ROOTS
+
+// Odd prime R, directly: with a_j = x_j + x_{R-j}, b_j = x_j - x_{R-j}
+// (1 <= j <= R/2), A_k = x_0 + sum_j a_j cos(2 pi j k / R) and
+// B_k = sum_j b_j sin(2 pi j k / R): X_k = A_k - i B_k, X_{R-k} = A_k + i B_k.
+template <int R>
+__device__ __forceinline__ void dft_odd(double2* x) {
+    constexpr int H = R / 2;
+    double2 a[H], b[H];
+    double2 x0 = x[0];
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+        a[j - 1] = cadd(x[j], x[R - j]);
+        b[j - 1] = csub(x[j], x[R - j]);
+        x0 = cadd(x0, a[j - 1]);
+    }
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+        double2 A = x[0], B = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 1; j <= H; ++j) {
+            const double2 w = root<R>((j * k) % R);
+            A = make_double2(A.x + a[j - 1].x * w.x, A.y + a[j - 1].y * w.x);
+            B = make_double2(B.x + b[j - 1].x * w.y, B.y + b[j - 1].y * w.y);
+        }
+        x[k] = make_double2(A.x + B.y, A.y - B.x);
+        x[R - k] = make_double2(A.x - B.y, A.y + B.x);
+    }
+    x[0] = x0;
+}
+
+template <>
+__device__ __forceinline__ void dft_reg<3>(double2* x) { dft_odd<3>(x); }
+template <>
+__device__ __forceinline__ void dft_reg<5>(double2* x) { dft_odd<5>(x); }
+template <>
+__device__ __forceinline__ void dft_reg<7>(double2* x) { dft_odd<7>(x); }
+template <>
+__device__ __forceinline__ void dft_reg<11>(double2* x) { dft_odd<11>(x); }
+template <>
+__device__ __forceinline__ void dft_reg<13>(double2* x) { dft_odd<13>(x); }
+template <>
+__device__ __forceinline__ void dft_reg<17>(double2* x) { dft_odd<17>(x); }
+
+// 15 = 3 x 5 Cooley-Tukey with twiddles exp(-2 pi i j k / 15).
+template <>
+__device__ __forceinline__ void dft_reg<15>(double2* x) {
+    double2 y[3][5];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) y[j][q] = x[j + 3 * q];
+        dft_odd<5>(y[j]);
+    }
+#pragma unroll
+    for (int j = 1; j < 3; ++j)
+#pragma unroll
+        for (int k = 1; k < 5; ++k) {
+            const double2 w = root<15>(j * k);
+            y[j][k] = cmul(y[j][k], make_double2(w.x, -w.y));
+        }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        double2 t[3] = {y[0][k], y[1][k], y[2][k]};
+        dft_odd<3>(t);
+        x[k] = t[0]; x[k + 5] = t[1]; x[k + 10] = t[2];
+    }
+}
+
 // Line buffers in LDS skip one slot after every 16 points, so that the
 // stride-16 writes of a radix-16 pass fall in distinct banks.
 __device__ __forceinline__ int P(int i) { return i + (i >> 4); }
@@ -109,12 +216,15 @@ __device__ __forceinline__ int P(int i) { return i + (i >> 4); }
 // One Stockham pass of radix R over a line of N points in LDS, already
 // combined into sub-transforms of length Ls: butterfly b reads x[b + q N/R],
 // scales input q by exp(-2 pi i k q / (R Ls)) (k = b mod Ls), and writes
-// output r to (b - k) R + k + r Ls.  Each thread holds 16 points.  The
-// pass's twiddles are stored as tw[k (R-1) + q - 1].
-template <int R>
+// output r to (b - k) R + k + r Ls.  With T >= N / 16 threads per line a
+// thread runs at most ceil(16 / R) butterflies, and one for R >= 11 (the
+// thread count is then at least N / R).  The pass's twiddles are stored as
+// tw[k (R-1) + q - 1].
+template <int R, bool kFirst = false>
 __device__ __forceinline__ void fft_pass(double2* buf, int N, int Ls, const double2* tw, int t, int T) {
-    constexpr int B = 16 / R;
+    constexpr int B = R >= 11 ? 1 : (16 + R - 1) / R;
     const int nb = N / R;
+    const bool ls_pow2 = (Ls & (Ls - 1)) == 0;
     double2 x[B][R];
     int ob[B];
 #pragma unroll
@@ -122,10 +232,10 @@ __device__ __forceinline__ void fft_pass(double2* buf, int N, int Ls, const doub
         const int b = t + c * T;
         ob[c] = -1;
         if (b < nb) {
-            const int k = b & (Ls - 1);
+            const int k = ls_pow2 ? (b & (Ls - 1)) : b % Ls;
 #pragma unroll
             for (int q = 0; q < R; ++q) x[c][q] = buf[P(b + q * nb)];
-            if (Ls > 1) {
+            if (!kFirst && Ls > 1) {
                 const double2* tk = tw + k * (R - 1) - 1;
 #pragma unroll
                 for (int q = 1; q < R; ++q) x[c][q] = cmul(x[c][q], tk[q]);
@@ -145,30 +255,70 @@ __device__ __forceinline__ void fft_pass(double2* buf, int N, int Ls, const doub
     __syncthreads();
 }
 
-// In-place forward FFT of a power-of-two line in LDS (all threads of the
-// workgroup must call it: it contains barriers).  tw: the per-pass twiddle
-// tables, concatenated in pass order (N - 1 entries).
-__device__ __forceinline__ void fft_lds(double2* buf, int N, const double2* tw, int t, int T) {
+// In-place forward FFT of the line of d.Nb points in LDS (all threads of the
+// workgroup must call it: it contains barriers), one pass per entry of
+// d.rad.  tw: the per-pass twiddle tables, concatenated in pass order
+// (Nb - 1 entries).  kMixed: the radix plan of a directly transformed
+// length, whose odd prime factor 7, 11, 13 or 17 (at most one) comes first,
+// where no twiddles apply; otherwise powers of two only.  Keeping each
+// instance to the passes it needs keeps the kernels within their registers.
+template <bool kMixed>
+__device__ __forceinline__ void fft_lds(double2* buf, const DftDev& d, const double2* tw, int t, int T) {
+    const int N = d.Nb;
     int Ls = 1;
-    while (Ls < N) {
-        const int rem = N / Ls;
-        if (rem >= 16) { fft_pass<16>(buf, N, Ls, tw, t, T); tw += Ls * 15; Ls *= 16; }
-        else if (rem == 8) { fft_pass<8>(buf, N, Ls, tw, t, T); tw += Ls * 7; Ls *= 8; }
-        else if (rem == 4) { fft_pass<4>(buf, N, Ls, tw, t, T); tw += Ls * 3; Ls *= 4; }
-        else { fft_pass<2>(buf, N, Ls, tw, t, T); tw += Ls; Ls *= 2; }
+    for (int p = 0; p < d.nrad; ++p) {
+        const int R = d.rad[p];
+        // opaque per pass: keeps the per-radix LDS addresses from being
+        // hoisted out of this loop (and spilled across it)
+        asm volatile("" : "+v"(t));
+        if (kMixed && p == 0) {
+            switch (R) {
+                case 16: fft_pass<16, true>(buf, N, Ls, tw, t, T); break;
+                case 8: fft_pass<8, true>(buf, N, Ls, tw, t, T); break;
+                case 4: fft_pass<4, true>(buf, N, Ls, tw, t, T); break;
+                case 2: fft_pass<2, true>(buf, N, Ls, tw, t, T); break;
+                case 3: fft_pass<3, true>(buf, N, Ls, tw, t, T); break;
+                case 5: fft_pass<5, true>(buf, N, Ls, tw, t, T); break;
+                case 7: fft_pass<7, true>(buf, N, Ls, tw, t, T); break;
+                case 11: fft_pass<11, true>(buf, N, Ls, tw, t, T); break;
+                case 13: fft_pass<13, true>(buf, N, Ls, tw, t, T); break;
+                case 15: fft_pass<15, true>(buf, N, Ls, tw, t, T); break;
+                default: fft_pass<17, true>(buf, N, Ls, tw, t, T); break;
+            }
+        } else if (kMixed) {
+            switch (R) {
+                case 16: fft_pass<16>(buf, N, Ls, tw, t, T); break;
+                case 8: fft_pass<8>(buf, N, Ls, tw, t, T); break;
+                case 4: fft_pass<4>(buf, N, Ls, tw, t, T); break;
+                case 2: fft_pass<2>(buf, N, Ls, tw, t, T); break;
+                case 3: fft_pass<3>(buf, N, Ls, tw, t, T); break;
+                case 5: fft_pass<5>(buf, N, Ls, tw, t, T); break;
+                default: fft_pass<15>(buf, N, Ls, tw, t, T); break;
+            }
+        } else {
+            switch (R) {
+                case 16: fft_pass<16>(buf, N, Ls, tw, t, T); break;
+                case 8: fft_pass<8>(buf, N, Ls, tw, t, T); break;
+                case 4: fft_pass<4>(buf, N, Ls, tw, t, T); break;
+                default: fft_pass<2>(buf, N, Ls, tw, t, T); break;
+            }
+        }
+        tw += Ls * (R - 1);
+        Ls *= R;
     }
 }
 
 // DFT of the length-L line held (pre-multiplied by the chirp when Bluestein)
 // in buf[0..Nb); leaves X_k, k < L, in buf[0..L).
-// Every thread owns at most kPts = 16 points of a line (T = Nb / 16 threads
+// Every thread owns at most kPts = 16 points of a line (T >= Nb / 16 threads
 // per line), so the pointwise loops below have a fixed trip count and issue
 // all of their table loads before the first use.
 constexpr int kPts = 16;
 
+template <bool kMixed>
 __device__ __forceinline__ void dft_lds(double2* buf, const DftDev& d, const double2* tw, int t, int T) {
-    fft_lds(buf, d.Nb, tw, t, T);
-    if (d.bluestein) {
+    fft_lds<kMixed>(buf, d, tw, t, T);
+    if (!kMixed && d.bluestein) {
         double2 bh[kPts];
 #pragma unroll
         for (int c = 0; c < kPts; ++c) {
@@ -181,7 +331,7 @@ __device__ __forceinline__ void dft_lds(double2* buf, const DftDev& d, const dou
             if (k < d.Nb) buf[P(k)] = cconj(cmul(buf[P(k)], bh[c]));
         }
         __syncthreads();
-        fft_lds(buf, d.Nb, tw, t, T);
+        fft_lds<false>(buf, d, tw, t, T);
 #pragma unroll
         for (int c = 0; c < kPts; ++c) {
             const int k = t + c * T;
@@ -238,7 +388,7 @@ __device__ __forceinline__ void line_thread(int LPW, int TPL, int* li, int* t) {
 // outputs are a prefix sum: each thread scans a contiguous chunk, chunk
 // totals meet in LDS.  out_k = post_k * 2 F_k.
 // LDS: [twiddles: Nb][line 0: line_stride(Nb)][line 1] ...
-template <bool kLineFast>
+template <bool kLineFast, bool kMixed>
 __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, LineSet ls,
                                               int mlen, DftDev d,
                                               const double* __restrict__ pre,
@@ -298,7 +448,7 @@ __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, Li
     }
     for (int s = M + t; s < d.Nb; s += TPL) buf[P(s)] = make_double2(0.0, 0.0);
     __syncthreads();
-    dft_lds(buf, d, tws, t, TPL);
+    dft_lds<kMixed>(buf, d, tws, t, TPL);
     // even outputs (strided) and odd increments (contiguous chunk per thread)
     const int Ko = (M + 1) / 2;                 // odd outputs 1, 3, .., <= M
     const int Q = (Ko + TPL - 1) / TPL;
@@ -357,6 +507,7 @@ __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, Li
 
 // values [p][n][m] (real) -> planes [p/2+1][n][m] (complex): theta DFT with the
 // (-1)^w phase of theta_0 = -pi and the 1/p normalisation.
+template <bool kMixed>
 __global__ __launch_bounds__(512) void k_theta_fwd(const double* __restrict__ val,
                                                     double2* __restrict__ planes, int m, int n,
                                                     int p, DftDev d, int TPL, int LPW) {
@@ -380,7 +531,7 @@ __global__ __launch_bounds__(512) void k_theta_fwd(const double* __restrict__ va
     }
     for (int l = p + t; l < d.Nb; l += TPL) buf[P(l)] = make_double2(0.0, 0.0);
     __syncthreads();
-    dft_lds(buf, d, tws, t, TPL);
+    dft_lds<kMixed>(buf, d, tws, t, TPL);
     const int nw = p / 2 + 1;
     const double invp = 1.0 / p;
     for (int w = t; w < nw; w += TPL) {
@@ -398,6 +549,7 @@ __global__ __launch_bounds__(512) void k_theta_fwd(const double* __restrict__ va
 
 // planes -> values: f_l = sum_w Y_w e^{+2 pi i w l / p}, Y_w = (-1)^w c_w and
 // its Hermitian extension; two r-lines per complex inverse DFT.
+template <bool kMixed>
 __global__ __launch_bounds__(512) void k_theta_inv(const double2* __restrict__ planes,
                                                     double* __restrict__ val, int m, int n, int p,
                                                     DftDev d, int TPL, int LPW) {
@@ -428,7 +580,7 @@ __global__ __launch_bounds__(512) void k_theta_inv(const double2* __restrict__ p
     }
     for (int l = p + t; l < d.Nb; l += TPL) buf[P(l)] = make_double2(0.0, 0.0);
     __syncthreads();
-    dft_lds(buf, d, tws, t, TPL);
+    dft_lds<kMixed>(buf, d, tws, t, TPL);
     for (int l = t; l < p; l += TPL) {
         const double2 z = cconj(buf[P(l)]);
         const int64_t off = (static_cast<int64_t>(l) * n + k) * m + j0;
@@ -437,12 +589,12 @@ __global__ __launch_bounds__(512) void k_theta_inv(const double2* __restrict__ p
     }
 }
 
-// Threads per line: one radix-16 butterfly each in the widest pass.  Lines
+// Threads per line: chosen with the radix plan (about Nb / 16).  Lines
 // per workgroup: strided lines take as many lines as keep ~128 KB of data in
 // LDS (full 128-byte segments per element index), contiguous lines fill 256
 // threads.
-void line_config(int Nb, bool strided, int* TPL, int* LPW, int* threads, size_t* lds) {
-    *TPL = Nb >= 16 ? Nb / 16 : 1;
+void line_config(int Nb, int tpl, bool strided, int* TPL, int* LPW, int* threads, size_t* lds) {
+    *TPL = tpl;
     int l;
     if (strided) {
         l = static_cast<int>(131072 / (static_cast<size_t>(line_stride(Nb)) * sizeof(double2)));
@@ -458,6 +610,15 @@ void line_config(int Nb, bool strided, int* TPL, int* LPW, int* threads, size_t*
     *lds = (static_cast<size_t>(*LPW) * line_stride(Nb) + Nb) * sizeof(double2);
 }
 
+// The mixed-radix kernels take lengths whose radix plan is not all powers
+// of two (never Bluestein).
+bool mixed_plan(const DftDev& d) {
+    if (d.bluestein) return false;
+    for (int i = 0; i < d.nrad; ++i)
+        if (d.rad[i] != 16 && d.rad[i] != 8 && d.rad[i] != 4 && d.rad[i] != 2) return true;
+    return false;
+}
+
 template <typename K>
 void raise_lds(K kernel, size_t bytes) {
     if (bytes > 65536)
@@ -471,11 +632,16 @@ hipError_t launch_theta_fwd(const double* values, double2* planes, int m, int n,
                             const DftDev& d, hipStream_t s) {
     int TPL, LPW, threads;
     size_t lds;
-    line_config(d.Nb, true, &TPL, &LPW, &threads, &lds);
-    raise_lds(k_theta_fwd, lds);
+    line_config(d.Nb, d.tpl, true, &TPL, &LPW, &threads, &lds);
     const int64_t lines = static_cast<int64_t>(n) * ((m + 1) / 2);
     const unsigned grid = static_cast<unsigned>((lines + LPW - 1) / LPW);
-    hipLaunchKernelGGL(k_theta_fwd, dim3(grid), dim3(threads), lds, s, values, planes, m, n, p, d, TPL, LPW);
+    if (mixed_plan(d)) {
+        raise_lds(k_theta_fwd<true>, lds);
+        hipLaunchKernelGGL(k_theta_fwd<true>, dim3(grid), dim3(threads), lds, s, values, planes, m, n, p, d, TPL, LPW);
+    } else {
+        raise_lds(k_theta_fwd<false>, lds);
+        hipLaunchKernelGGL(k_theta_fwd<false>, dim3(grid), dim3(threads), lds, s, values, planes, m, n, p, d, TPL, LPW);
+    }
     return hipGetLastError();
 }
 
@@ -483,11 +649,16 @@ hipError_t launch_theta_inv(const double2* planes, double* values, int m, int n,
                             const DftDev& d, hipStream_t s) {
     int TPL, LPW, threads;
     size_t lds;
-    line_config(d.Nb, true, &TPL, &LPW, &threads, &lds);
-    raise_lds(k_theta_inv, lds);
+    line_config(d.Nb, d.tpl, true, &TPL, &LPW, &threads, &lds);
     const int64_t lines = static_cast<int64_t>(n) * ((m + 1) / 2);
     const unsigned grid = static_cast<unsigned>((lines + LPW - 1) / LPW);
-    hipLaunchKernelGGL(k_theta_inv, dim3(grid), dim3(threads), lds, s, planes, values, m, n, p, d, TPL, LPW);
+    if (mixed_plan(d)) {
+        raise_lds(k_theta_inv<true>, lds);
+        hipLaunchKernelGGL(k_theta_inv<true>, dim3(grid), dim3(threads), lds, s, planes, values, m, n, p, d, TPL, LPW);
+    } else {
+        raise_lds(k_theta_inv<false>, lds);
+        hipLaunchKernelGGL(k_theta_inv<false>, dim3(grid), dim3(threads), lds, s, planes, values, m, n, p, d, TPL, LPW);
+    }
     return hipGetLastError();
 }
 
@@ -496,16 +667,24 @@ hipError_t launch_dct(const double2* in, double2* out, const LineSet& ls, int ml
                       const double* post, const double2* fold, hipStream_t s) {
     int TPL, LPW, threads;
     size_t lds;
-    line_config(d.Nb, !contiguous_lines, &TPL, &LPW, &threads, &lds);
+    line_config(d.Nb, d.tpl, !contiguous_lines, &TPL, &LPW, &threads, &lds);
     const int64_t lines = static_cast<int64_t>(ls.n_outer) * ls.n_inner;
     const unsigned grid = static_cast<unsigned>((lines + LPW - 1) / LPW);
+#define CYL_DCT(F, X)                                                                                 \
+    do {                                                                                              \
+        raise_lds(k_dct<F, X>, lds);                                                                  \
+        hipLaunchKernelGGL((k_dct<F, X>), dim3(grid), dim3(threads), lds, s, in, out, ls, mlen, d, pre, post, \
+                           fold, TPL, LPW);                                                           \
+    } while (0)
+    const bool mixed = mixed_plan(d);
     if (contiguous_lines) {
-        raise_lds(k_dct<false>, lds);
-        hipLaunchKernelGGL(k_dct<false>, dim3(grid), dim3(threads), lds, s, in, out, ls, mlen, d, pre, post, fold, TPL, LPW);
+        if (mixed) CYL_DCT(false, true);
+        else CYL_DCT(false, false);
     } else {
-        raise_lds(k_dct<true>, lds);
-        hipLaunchKernelGGL(k_dct<true>, dim3(grid), dim3(threads), lds, s, in, out, ls, mlen, d, pre, post, fold, TPL, LPW);
+        if (mixed) CYL_DCT(true, true);
+        else CYL_DCT(true, false);
     }
+#undef CYL_DCT
     return hipGetLastError();
 }
 

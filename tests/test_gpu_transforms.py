@@ -9,9 +9,14 @@ from tests.gpu_common import banner, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
-# power-of-two and Bluestein lengths, odd/even/1/2 theta counts, ragged tails
+# power-of-two, mixed-radix and Bluestein lengths, odd/even/1/2 theta counts,
+# ragged tails.  DFT lengths (r: m - 1, z: n - 1, theta: p) and their passes:
+# 255 = 17 x 15, 17, 34 = 17 x 2; 11, 22 = 11 x 2; 13, 26 = 13 x 2;
+# 7, 35 = 7 x 5, 45 = 15 x 3; 65 = 13 x 5; 39 = 13 x 3; 30 = 2 x 15;
+# 47, 19, 31, 129 = 3 x 43, 119 = 7 x 17 by Bluestein.
 SIZES = [(4, 4, 1), (8, 6, 4), (9, 7, 5), (17, 33, 16), (33, 20, 12), (32, 32, 32),
-         (48, 40, 30), (65, 17, 2), (20, 129, 7), (130, 66, 64)]
+         (48, 40, 30), (65, 17, 2), (20, 129, 7), (130, 66, 64), (256, 18, 34),
+         (12, 23, 22), (14, 27, 26), (8, 36, 45), (120, 10, 6)]
 
 
 @pytest.mark.parametrize("m,n,p", SIZES)
@@ -46,3 +51,19 @@ def test_inverse_ignores_imaginary_parts_of_real_slots():
     hr[0] = hr[0].real
     hr[p // 2] = hr[p // 2].real
     assert np.max(np.abs(v - tr.inverse(tr.from_half(hr, p)))) < 1e-13 * np.max(np.abs(v))
+
+
+def test_mixed_radix_equals_bluestein_at_256():
+    """n = 256 (DFT length 255 = 17 x 15): the mixed-radix transforms agree
+    with the Bluestein ones to rounding."""
+    import os
+    need_gpu()
+    m, n, p = 256, 256, 6
+    f = np.random.default_rng(7).standard_normal((p, n, m))
+    a = host(cyl.Plan(m, n, p).transform_fwd(dev(f)))
+    os.environ["CYLSPEC_DFT_MIXED"] = "0"
+    try:
+        b = host(cyl.Plan(m, n, p).transform_fwd(dev(f)))
+    finally:
+        os.environ.pop("CYLSPEC_DFT_MIXED")
+    assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(b))
