@@ -41,8 +41,8 @@ ADI_FLOPS_PER_UNKNOWN_ITER = 38.0
 # HBM bytes per ADI launch at 256^3 from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # (scaled by a 512 MiB copy: fetch x2.0, write x1.0), valid for the ADI source
 # whose SHA-256 starts with ADI_TRAFFIC_SHA; reported as null otherwise.
-ADI_TRAFFIC_BYTES_256 = 2.559e9
-ADI_TRAFFIC_SHA = "0ffc5851bedef06e"
+ADI_TRAFFIC_BYTES_256 = 2.570e9
+ADI_TRAFFIC_SHA = "d6c61b10f5240ef4"
 
 
 def parse():
