@@ -18,7 +18,11 @@ Prints one JSON line.  Besides the headline value it carries:
   batched_64    64 independent BDF1 heat problems of uneven sizes (n_r = n_z
                 in 48..384, n_theta in 32..256, alpha in [0.1, 2]), 50 steps:
                 batched launches with a replayed step graph against stepping
-                each problem on its own.
+                each problem on its own;
+  physical_256  the same 256^3 solve for a physical forcing (a smooth
+                function of x, y, z): the physical-parity fast path (the
+                j = w mod 2 blocks only) against the general solve of the
+                same input.
 """
 
 import argparse
@@ -57,6 +61,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-reps", type=int, default=2)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-physical", action="store_true")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--cpu-modes", type=int, default=16,
@@ -276,6 +281,28 @@ def main():
                       "parallelism": "single GPU"},
            "resid_ratio": info["resid_ratio"], "phase_ms_per_step": phases,
            "roofline": roofline}
+
+    if not args.no_physical:
+        fp = torch.from_numpy(synth.physical_values(m, n, p, synth.SEED_BASE + 4)).cuda()
+        legs = {}
+        for phys in (False, True):
+            plan.set_physical(phys)
+            _, pinfo = plan.poisson_solve(fp, adi_tol=args.tol, out=u, info=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                plan.poisson_solve(fp, adi_tol=args.tol, out=u)
+            torch.cuda.synchronize()
+            legs[phys] = (1e3 * (time.perf_counter() - t0) / args.steps, pinfo["resid_ratio"])
+        plan.set_physical(False)
+        out["physical_256"] = {"ms_per_solve": legs[True][0], "unknowns_per_s": m * n * p / (legs[True][0] * 1e-3),
+                               "general_ms_per_solve": legs[False][0],
+                               "speedup_vs_general": legs[False][0] / legs[True][0],
+                               "resid_ratio": legs[True][1],
+                               "config": {"workload": "poisson_%d^3_physical_forcing" % m,
+                                          "forcing": "seeded smooth function of x, y, z",
+                                          "adi_tol": args.tol}}
+        del fp
 
     if not args.no_heat:
         hp = cyl.Plan(128, 128, 128)

@@ -117,6 +117,37 @@ int cyl_transform_inv_adjoint(cyl_plan_t plan, const double* values_bar, double*
 int cyl_poisson_solve(cyl_plan_t plan, int space, const double* f, const double* bc_lift,
                       double* u, double adi_tol, cyl_solve_info* info);
 
+/* Physical-parity fast path for cyl_poisson_solve on this plan (enable != 0)
+ * or the general solve (0, the default).  On the doubled grid (r in [-1, 1])
+ * a function that is single-valued and smooth on the cylinder satisfies
+ * f(-r, theta) = f(r, theta + pi), so its coefficient of T_j(r) e^{i w theta}
+ * vanishes unless j = w (mod 2), and the Poisson operator keeps that subspace
+ * (the parity restriction the paper's introduction cites for the doubled
+ * discretization).  Enabled, a solve runs the ADI and the residual
+ * correction on the j = w (mod 2) parity blocks only (half of the blocks)
+ * and returns a solution whose other coefficients are exactly zero; the
+ * other-parity part of f (rounding for physical forcing) is discarded.  The
+ * residual ratio reported in cyl_solve_info still covers all of f.  Needs an
+ * even n_theta (CYL_E_UNSUPPORTED otherwise: for odd n_theta theta + pi is no
+ * grid angle and the sampled parities mix).  Applies to cyl_poisson_solve
+ * only; heat handles solve all blocks. */
+int cyl_plan_set_physical(cyl_plan_t plan, int enable);
+
+/* Lift from boundary traces (non-homogeneous Dirichlet data given on the
+ * boundary only): lift = the transfinite (Coons) interpolant in (r, z) of
+ * the four faces of the doubled grid's box on every theta line,
+ *   L = (1-a) R_-(z) + a R_+(z) + (1-b) Z_-(r) + b Z_+(r) - (bilinear corner terms),
+ * a = (1 + r)/2, b = (1 + z)/2, corners from the z-faces.  rface: device
+ * [2][n_theta][n_z] (the values at r = -1, then at r = +1: the side wall at
+ * theta + pi and at theta); zface: device [2][n_theta][n_r] (z = -1, then
+ * z = +1); lift: device [n_theta][n_z][n_r], written (value space).  For
+ * data that agree on the box's edges the lift takes the given values on all
+ * faces; pass it as bc_lift to cyl_poisson_solve or cyl_heat_create (the
+ * r^2-weighted equations of Section 3 admit any lift with those boundary
+ * values, and the discrete solution depends on the boundary values only).
+ * Enqueued on the plan's stream; allocates nothing. */
+int cyl_trace_lift(cyl_plan_t plan, const double* rface, const double* zface, double* lift);
+
 /* Heat equation (d_t - alpha nabla^2) T = g (Section 3), advanced by BDF of
  * order bdf_order in {1, 4} with step dt (kappa^(1) = dt,
  * kappa^(4) = 12 dt / 25); g and the boundary data are time independent.

@@ -30,7 +30,8 @@ EXPORTS = ["cyl_plan_create", "cyl_plan_destroy", "cyl_transform_fwd", "cyl_tran
            "cyl_plan_get_profile", "cyl_status_string", "cyl_last_error",
            "cyl_transform_fwd_adjoint", "cyl_transform_inv_adjoint", "cyl_heat_grad_create",
            "cyl_heat_grad_forward", "cyl_heat_grad_backward", "cyl_heat_grad_destroy",
-           "cyl_batch_create", "cyl_batch_step", "cyl_batch_describe", "cyl_batch_destroy"]
+           "cyl_batch_create", "cyl_batch_step", "cyl_batch_describe", "cyl_batch_destroy",
+           "cyl_plan_set_physical", "cyl_trace_lift"]
 
 CYL_BATCH_NO_GRAPH = 1
 CYL_BATCH_NO_TUNE = 2
@@ -96,6 +97,8 @@ def load():
         "cyl_batch_step": [P, I],
         "cyl_batch_describe": [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(ctypes.c_char_p)],
         "cyl_batch_destroy": [P],
+        "cyl_plan_set_physical": [P, I],
+        "cyl_trace_lift": [P, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -213,10 +216,34 @@ class Plan:
         _check(self._lib.cyl_transform_inv_adjoint(self._h, _ptr(values_bar), _ptr(out)))
         return out
 
-    def poisson_solve(self, f, bc_lift=None, adi_tol=1e-12, space=None, out=None, info=False):
-        """Solve nabla^2 u = f (u = lift on the boundary). Returns u (and info if asked)."""
+    def set_physical(self, enable=True):
+        """Physical-parity fast path for ``poisson_solve`` (j = w mod 2 blocks
+        only; even n_theta)."""
+        _check(self._lib.cyl_plan_set_physical(self._h, 1 if enable else 0))
+
+    def trace_lift(self, rface, zface, out=None):
+        """Coons lift of the boundary faces: rface [2, n_theta, n_z] (r = -1,
+        r = +1), zface [2, n_theta, n_r] (z = -1, z = +1), device float64."""
+        for t, shp, name in ((rface, (2, self.n_theta, self.n_z), "rface"),
+                             (zface, (2, self.n_theta, self.n_r), "zface")):
+            if not (t.is_cuda and t.is_contiguous() and t.dtype == torch.float64 and tuple(t.shape) == shp):
+                raise ValueError("%s must be a contiguous float64 device tensor %s" % (name, shp))
+        out = self._out(CYL_SPACE_VALUE, out)
+        _check(self._lib.cyl_trace_lift(self._h, _ptr(rface), _ptr(zface), _ptr(out)))
+        return out
+
+    def poisson_solve(self, f, bc_lift=None, adi_tol=1e-12, space=None, out=None, info=False,
+                      bc_traces=None):
+        """Solve nabla^2 u = f (u = lift on the boundary). Returns u (and info if asked).
+
+        bc_traces: (rface, zface) boundary faces instead of a lift (value
+        space); the lift is built with ``trace_lift``."""
         if space is None:
             space = CYL_SPACE_COEFF if f.dtype == torch.complex128 else CYL_SPACE_VALUE
+        if bc_traces is not None:
+            if bc_lift is not None or space != CYL_SPACE_VALUE:
+                raise ValueError("bc_traces needs value space and no bc_lift")
+            bc_lift = self.trace_lift(*bc_traces)
         self._check_tensor(f, space, "f")
         self._check_tensor(bc_lift, space, "bc_lift")
         out = self._out(space, out)

@@ -117,6 +117,9 @@ struct Setup {
     DevMem rtab, ztab, vmu, blocks, atab, ztabA_own;
     const double* ztabA = nullptr;   // B/D column records of this orientation
     std::vector<BlockDesc> hblocks;
+    // physical parity: the blocks with r-parity = w (mod 2), and the others
+    DevMem blocks_phys, blocks_skip;
+    int n_phys = 0, n_skip = 0;
 };
 
 enum Phase { PH_FWD, PH_RHS, PH_ADI, PH_RES, PH_REC, PH_INV, PH_HRHS, PH_PROJ, PH_ADJ, PH_COUNT };
@@ -145,6 +148,8 @@ struct cyl_plan_s {
     size_t lds_bytes = 0;
     std::map<std::pair<double, int>, std::unique_ptr<Setup>> setups;
     bool profiling = false;
+    bool physical = false;         // Poisson solves keep the j = w (mod 2) blocks only
+    DevMem lift_ra, lift_zb;       // (1 + r_j)/2, (1 + z_k)/2 of the boundary-trace lift
     struct Rec { int phase; hipEvent_t a, b; };
     std::vector<Rec> recs;
 };
@@ -363,6 +368,14 @@ std::unique_ptr<Setup> make_setup(cyl_plan_t pl, double ka, double eps, bool fli
     upload(s->ztab, s->h.ztab);
     upload(s->vmu, s->h.vmu);
     upload(s->blocks, s->hblocks);
+    {
+        std::vector<BlockDesc> keep, skip;
+        for (const BlockDesc& b : s->hblocks) (b.pr == (std::abs(b.w) & 1) ? keep : skip).push_back(b);
+        s->n_phys = static_cast<int>(keep.size());
+        s->n_skip = static_cast<int>(skip.size());
+        upload(s->blocks_phys, keep);
+        upload(s->blocks_skip, skip);
+    }
     upload(s->atab, apply_rows(pl, ka, flip));
     if (flip) {
         upload(s->ztabA_own, z_columns(pl, true));
@@ -453,15 +466,17 @@ void transform_inv_adjoint(cyl_plan_t pl, const double* values, double* tmp, dou
     hip_check(launch_scale_planes(coeffs, g.m, g.n, g.p, 1, pl->stream), "scale planes");
 }
 
-// ADI solve of all blocks: X <- solution of A X B + C X D = E (setup pencil).
-void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X) {
+// ADI solve of all blocks (physical: the j = w (mod 2) blocks only):
+// X <- solution of A X B + C X D = E (setup pencil).
+void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X, bool physical = false) {
     const Geometry& g = pl->geo;
-    const int nblk = static_cast<int>(s->hblocks.size());
+    const int nblk = physical ? s->n_phys : static_cast<int>(s->hblocks.size());
+    DevMem& blocks = physical ? s->blocks_phys : s->blocks;
     for (int pass = 0; pass < s->passes; ++pass) {
         const double* rhs = E;
         if (pass > 0) {
             Scope sc(pl, PH_RES);
-            hip_check(launch_apply2(s->blocks.as<BlockDesc>(), nblk, g.me[0], g.ne[0], E, 1.0, X, 1.0, 1.0,
+            hip_check(launch_apply2(blocks.as<BlockDesc>(), nblk, g.me[0], g.ne[0], E, 1.0, X, 1.0, 1.0,
                                     pl->R.as<double>(), s->atab.as<double>(),
                                     static_cast<int64_t>(g.me[0] + g.me[1]) * 12,
                                     s->ztabA, pl->stream), "residual");
@@ -469,18 +484,18 @@ void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X) {
         }
         Scope sc(pl, PH_ADI);
         if (pl->adi_split && pl->split_gs)
-            hip_check(launch_adi_split_gs(s->blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
+            hip_check(launch_adi_split_gs(blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
                                           pl->state.as<double>(), pl->state_stride, s->rtab.as<double>(),
                                           s->ztab.as<double>(), s->vmu.as<double>(), pass > 0, pl->lds_bytes,
                                           pl->stream),
                       "adi");
         else if (pl->adi_split)
-            hip_check(launch_adi_split(s->blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
+            hip_check(launch_adi_split(blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
                                        s->rtab.as<double>(), s->ztab.as<double>(), s->vmu.as<double>(),
                                        pass > 0, pl->lds_bytes, pl->stream),
                       "adi");
         else
-            hip_check(launch_adi(s->blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
+            hip_check(launch_adi(blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
                                  pl->state.as<double>(), pl->state_stride, s->rtab.as<double>(),
                                  s->ztab.as<double>(),
                                  s->vmu.as<double>(), pass > 0, pl->use_lds, pl->lds_bytes, pl->stream),
@@ -544,6 +559,15 @@ void build_plan(cyl_plan_t pl) {
         upload(f, v);
     };
     fold_tab(m, pl->fold_r);
+    // (1 + r_j)/2 and (1 + z_k)/2 of the doubled grid, r_j = cos((m - 1 - j) pi / (m - 1))
+    auto unit_tab = [](int len, DevMem& t) {
+        const double pi = 3.14159265358979323846;
+        std::vector<double> v(static_cast<size_t>(len));
+        for (int j = 0; j < len; ++j) v[j] = 0.5 * (1.0 + std::cos((len - j - 1) * pi / (len - 1)));
+        upload(t, v);
+    };
+    unit_tab(m, pl->lift_ra);
+    unit_tab(n, pl->lift_zb);
     fold_tab(n, pl->fold_z);
     pl->dth.build(p);
     // DCT pre/post factors: forward c_k = (-1)^k s_k / M * DCT-I(f)_k with
@@ -1027,7 +1051,13 @@ int cyl_poisson_solve(cyl_plan_t plan, int space, const double* f, const double*
             hip_check(launch_rhs3(F, Lc, 1.0, 0.0, -1.0, pl->E.as<double>(), s->blocks.as<BlockDesc>(),
                                   pl->plane_of.as<int>(), g.nw, g.m, g.n, pl->rhs, pl->stream), "rhs");
         }
-        adi_solve(pl, s, pl->E.as<double>(), pl->X.as<double>());
+        if (pl->physical) {
+            hip_check(launch_zero_blocks(s->blocks_skip.as<BlockDesc>(), s->n_skip, g.me[0], g.ne[0],
+                                         pl->X.as<double>(), pl->stream), "zero blocks");
+            adi_solve(pl, s, pl->E.as<double>(), pl->X.as<double>(), true);
+        } else {
+            adi_solve(pl, s, pl->E.as<double>(), pl->X.as<double>());
+        }
         if (info) check_residual(pl, s, pl->E.as<double>(), pl->X.as<double>(), adi_tol, info);
         double2* out = space == CYL_SPACE_COEFF ? reinterpret_cast<double2*>(u) : pl->planesA.as<double2>();
         {
@@ -1197,6 +1227,24 @@ int cyl_adi_parameters(int n_r, int n_z, int w, double kappa_alpha, double adi_t
             std::copy(uu.begin(), uu.end(), u);
             std::copy(vv.begin(), vv.end(), v);
         }
+    });
+}
+
+int cyl_plan_set_physical(cyl_plan_t plan, int enable) {
+    return guarded([&] {
+        if (!plan) fail(CYL_E_INVALID_ARG, "plan is NULL");
+        if (enable && plan->p % 2 != 0)
+            fail(CYL_E_UNSUPPORTED, "physical parity needs an even n_theta (theta + pi on the grid)");
+        plan->physical = enable != 0;
+    });
+}
+
+int cyl_trace_lift(cyl_plan_t plan, const double* rface, const double* zface, double* lift) {
+    return guarded([&] {
+        if (!plan || !rface || !zface || !lift) fail(CYL_E_INVALID_ARG, "NULL argument");
+        hip_check(launch_trace_lift(rface, zface, plan->lift_ra.as<double>(), plan->lift_zb.as<double>(), lift,
+                                    plan->m, plan->n, plan->p, plan->stream),
+                  "trace lift");
     });
 }
 

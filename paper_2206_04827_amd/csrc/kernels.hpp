@@ -138,6 +138,16 @@ int64_t adi_split_gs_state_stride(int mp0, int np0);
 hipError_t adi_set_lds_limit(int np0, size_t bytes);
 hipError_t adi_split_set_lds_limit(int np0, size_t bytes);
 
+// Coons lift of the doubled box's faces: rface [2][p][n] (r = -1, +1), zface
+// [2][p][m] (z = -1, +1), ra_j = (1 + r_j)/2, zb_k = (1 + z_k)/2 -> lift
+// [p][n][m] (boundary.hip).
+hipError_t launch_trace_lift(const double* rface, const double* zface, const double* ra, const double* zb,
+                             double* lift, int m, int n, int p, hipStream_t s);
+// Zero the me x ne solution region (at xoff) of every listed block; me0, ne0
+// bound the block sizes.
+hipError_t launch_zero_blocks(const BlockDesc* blocks, int nblocks, int me0, int ne0, double* X,
+                              hipStream_t s);
+
 // out = sE * E - sAB * (A X B) - sCD * (C X D) blockwise.  atab: per (w, r
 // parity) rows of 12 (A row i at i-2..i+3, then C row i at i-2..i+3), w stride
 // a_wstride (0: the same rows for every w); ztabA: per z parity columns of 8

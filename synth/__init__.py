@@ -14,6 +14,11 @@ Workloads (the paper measures on no public dataset; everything is synthetic):
   eigenfunctions J_w(j_{w,s} r) sin(q pi (z+1)/2) cos(w theta + phi), with
   w in {0..6}, s, q in {1,2,3}, a ~ N(0,1), phi ~ U[0, 2 pi).  On the doubled
   grid J_w(-x) = (-1)^w J_w(x), consistent with (r, theta) ~ (-r, theta + pi).
+* ``physical_values``: a seeded smooth function of the Cartesian coordinates
+  (x, y, z) = (r cos theta, r sin theta, z), sum over 4 terms of
+  a exp(b x + c y) cos(d z + e x y + phi) with a ~ N(0,1), b, c ~ U[-0.6, 0.6],
+  d ~ U[0.5, 2.5], e ~ U[-1, 1], phi ~ U[0, 2 pi): single-valued and smooth
+  on the cylinder, hence of physical parity on the doubled grid.
 * ``ccf_grid``: the sample points x_(j,k,l) of the doubled CCF grid
   (r_j = cos((m-j-1) pi/(m-1)), z_k likewise, theta_l = (2l - p) pi / p).
 """
@@ -34,6 +39,23 @@ def ccf_grid(m, n, p):
     z = np.cos((n - np.arange(n) - 1) * np.pi / (n - 1))
     th = (2 * np.arange(p) - p) * np.pi / p
     return r, z, th
+
+
+def physical_values(m, n, p, seed, terms=4):
+    """Seeded smooth Cartesian field on the grid, values [p][n][m] float64."""
+    g = rng(seed)
+    r, z, th = ccf_grid(m, n, p)
+    TH, Z, R = np.meshgrid(th, z, r, indexing="ij")
+    X, Y = R * np.cos(TH), R * np.sin(TH)
+    f = np.zeros((p, n, m))
+    for _ in range(terms):
+        a = g.standard_normal()
+        b, c = g.uniform(-0.6, 0.6, 2)
+        d = g.uniform(0.5, 2.5)
+        e = g.uniform(-1.0, 1.0)
+        phi = g.uniform(0.0, 2 * np.pi)
+        f += a * np.exp(b * X + c * Y) * np.cos(d * Z + e * X * Y + phi)
+    return f
 
 
 def smooth_coeffs(m, n, p, seed, decay=4.0):
