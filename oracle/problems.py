@@ -119,3 +119,42 @@ def heat(history_values, g, alpha, h, steps, order=1, lift=None, method="bs", re
     c_l = None if lift is None else tr.forward(lift)
     out = heat_coeffs(hist_c, c_g, alpha, h, steps, order, c_l, None, method, refine_steps)
     return tr.inverse(out[0])
+
+
+# ----------------------------------------------------------------------------
+# Horizontal (disk) Poisson (Section 4, eq. (ptpoisson))
+# ----------------------------------------------------------------------------
+
+def disk_poisson_mode(m, n, w, F):
+    """Solve Delta_h u = f for one wavenumber, u = 0 at r = +-1.
+
+    Delta_h = nabla^2 - d_zz has no z derivative, so after the theta DFT every
+    Chebyshev z coefficient k is its own problem in r (the diagonalisation in
+    theta and z of Section 4): r^2 (d_rr + r^-1 d_r - w^2 r^-2) u_k = r^2 f_k,
+    in the Dirichlet basis of Section 3 with the first m-2 C^(2) rows kept:
+    At x_k = [R2 f_k]_tau, u_k = Q_m x_k.  F: m x n full T coefficients
+    (rows r-degrees).  READING: the paper states no boundary condition for
+    this solve in isolation; homogeneous Dirichlet at the side wall is used
+    (no condition in z, where the operator has no derivative).
+    """
+    At, _, _, _ = ops.tau_system(m, max(n, 3), w)
+    R2m = ops._cut(ops.R2(m), m, m)
+    E = (R2m @ F)[: m - 2]
+    Xt = np.linalg.solve(At, E)
+    Qm = ops.dirichlet_basis(m)[:m]
+    return Qm @ Xt
+
+
+def disk_poisson_coeffs(c_f):
+    """Full-coefficient disk solve c[l, k, j] -> c_u[l, k, j] (every wavenumber)."""
+    p, n, m = c_f.shape
+    wn = tr.wavenumbers(p)
+    out = np.zeros_like(c_f)
+    for l in range(p):
+        out[l] = disk_poisson_mode(m, n, wn[l], _mode_matrix(c_f, l)).T
+    return out
+
+
+def disk_poisson(f):
+    """Value-space horizontal Poisson solve Delta_h u = f, u = 0 at r = +-1."""
+    return np.real(tr.inverse(disk_poisson_coeffs(tr.forward(f))))
