@@ -22,7 +22,12 @@ Prints one JSON line.  Besides the headline value it carries:
   physical_256  the same 256^3 solve for a physical forcing (a smooth
                 function of x, y, z): the physical-parity fast path (the
                 j = w mod 2 blocks only) against the general solve of the
-                same input.
+                same input;
+  disk_poisson_256
+                the horizontal (disk) Poisson solve Delta_h u = f of
+                Section 4 on the same grid and forcing (transforms plus one
+                banded r-solve per wavenumber and z coefficient), with the
+                solve kernel's algorithmic bandwidth.
 """
 
 import argparse
@@ -62,6 +67,7 @@ def parse():
     ap.add_argument("--adjoint-reps", type=int, default=2)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-physical", action="store_true")
+    ap.add_argument("--no-disk", action="store_true")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--cpu-modes", type=int, default=16,
@@ -303,6 +309,29 @@ def main():
                                           "forcing": "seeded smooth function of x, y, z",
                                           "adi_tol": args.tol}}
         del fp
+
+    if not args.no_disk:
+        plan.disk_poisson_solve(f, out=u)
+        torch.cuda.synchronize()
+        plan.set_profiling(True)
+        plan.profile()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.disk_poisson_solve(f, out=u)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        dp = plan.profile()
+        plan.set_profiling(False)
+        kms = dp["ms_adi"] / max(1, dp["n_adi"])
+        # read f, write and re-read the forward sweep, write u: 4 x 16 B per complex coefficient
+        dbytes = 64.0 * (p // 2 + 1) * n * m
+        out["disk_poisson_256"] = {"ms_per_solve": ms, "unknowns_per_s": m * n * p / (ms * 1e-3),
+                                   "kernel": "k_disk", "kernel_ms": kms,
+                                   "kernel_bytes": dbytes, "kernel_gbs": dbytes / (kms * 1e-3) / 1e9,
+                                   "kernel_hbm_frac": dbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                   "transforms_ms": (dp["ms_transform_fwd"] + dp["ms_transform_inv"]) / args.steps,
+                                   "config": {"workload": "disk_poisson_%d^3_value_space" % m,
+                                              "forcing": "seeded decaying random CCF spectrum"}}
 
     if not args.no_heat:
         hp = cyl.Plan(128, 128, 128)

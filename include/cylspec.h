@@ -148,6 +148,19 @@ int cyl_plan_set_physical(cyl_plan_t plan, int enable);
  * Enqueued on the plan's stream; allocates nothing. */
 int cyl_trace_lift(cyl_plan_t plan, const double* rface, const double* zface, double* lift);
 
+/* Horizontal (disk) Poisson solve of Section 4 (eq. ptpoisson, the building
+ * block of the poloidal-toroidal decomposition): Delta_h u = f with
+ * Delta_h = nabla^2 - d_zz, u = 0 on the side wall r = 1 (no condition in z,
+ * where Delta_h has no derivative).  Diagonalised in theta (DFT) and z (every
+ * Chebyshev z coefficient is its own problem): per wavenumber and z
+ * coefficient one banded tau system in r, [A_w Q]_tau x = [R^2 C02 f]_tau,
+ * u = Q x, solved directly (no ADI, no tolerance).  space: CYL_SPACE_VALUE or
+ * CYL_SPACE_COEFF for f and u alike; in coefficient space u must not alias f.
+ * The first call builds the plan's disk records (host work and a small
+ * device allocation); later calls allocate nothing.  Timed as the ADI phase
+ * when profiling. */
+int cyl_disk_poisson_solve(cyl_plan_t plan, int space, const double* f, double* u);
+
 /* Heat equation (d_t - alpha nabla^2) T = g (Section 3), advanced by BDF of
  * order bdf_order in {1, 4} with step dt (kappa^(1) = dt,
  * kappa^(4) = 12 dt / 25); g and the boundary data are time independent.

@@ -31,7 +31,7 @@ EXPORTS = ["cyl_plan_create", "cyl_plan_destroy", "cyl_transform_fwd", "cyl_tran
            "cyl_transform_fwd_adjoint", "cyl_transform_inv_adjoint", "cyl_heat_grad_create",
            "cyl_heat_grad_forward", "cyl_heat_grad_backward", "cyl_heat_grad_destroy",
            "cyl_batch_create", "cyl_batch_step", "cyl_batch_describe", "cyl_batch_destroy",
-           "cyl_plan_set_physical", "cyl_trace_lift"]
+           "cyl_plan_set_physical", "cyl_trace_lift", "cyl_disk_poisson_solve"]
 
 CYL_BATCH_NO_GRAPH = 1
 CYL_BATCH_NO_TUNE = 2
@@ -99,6 +99,7 @@ def load():
         "cyl_batch_destroy": [P],
         "cyl_plan_set_physical": [P, I],
         "cyl_trace_lift": [P, P, P, P],
+        "cyl_disk_poisson_solve": [P, I, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -252,6 +253,15 @@ class Plan:
                                            float(adi_tol), ctypes.byref(inf) if info else None))
         if info:
             return out, {k: getattr(inf, k) for k, _ in SolveInfo._fields_}
+        return out
+
+    def disk_poisson_solve(self, f, space=None, out=None):
+        """Horizontal (disk) Poisson Delta_h u = f, u = 0 at r = 1 (no z condition)."""
+        if space is None:
+            space = CYL_SPACE_COEFF if f.dtype == torch.complex128 else CYL_SPACE_VALUE
+        self._check_tensor(f, space, "f")
+        out = self._out(space, out)
+        _check(self._lib.cyl_disk_poisson_solve(self._h, space, _ptr(f), _ptr(out)))
         return out
 
     def set_profiling(self, enable=True):

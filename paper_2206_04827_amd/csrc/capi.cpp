@@ -149,6 +149,8 @@ struct cyl_plan_s {
     std::map<std::pair<double, int>, std::unique_ptr<Setup>> setups;
     bool profiling = false;
     bool physical = false;         // Poisson solves keep the j = w (mod 2) blocks only
+    std::unique_ptr<DiskTables> disk;   // horizontal Poisson records (built on first use)
+    DevMem disk_lu, disk_taps;
     DevMem lift_ra, lift_zb;       // (1 + r_j)/2, (1 + z_k)/2 of the boundary-trace lift
     struct Rec { int phase; hipEvent_t a, b; };
     std::vector<Rec> recs;
@@ -1227,6 +1229,37 @@ int cyl_adi_parameters(int n_r, int n_z, int w, double kappa_alpha, double adi_t
             std::copy(uu.begin(), uu.end(), u);
             std::copy(vv.begin(), vv.end(), v);
         }
+    });
+}
+
+int cyl_disk_poisson_solve(cyl_plan_t plan, int space, const double* f, double* u) {
+    return guarded([&] {
+        if (!plan || !f || !u) fail(CYL_E_INVALID_ARG, "NULL argument");
+        validate_space(space);
+        if (space == CYL_SPACE_COEFF && f == u) fail(CYL_E_INVALID_ARG, "u must not alias f in coefficient space");
+        cyl_plan_s* pl = plan;
+        const Geometry& g = pl->geo;
+        if (!pl->disk) {
+            auto t = std::make_unique<DiskTables>(build_disk_tables(pl->rops, g.nw));
+            upload(pl->disk_lu, t->lu);
+            upload(pl->disk_taps, t->taps);
+            pl->disk = std::move(t);
+        }
+        const DiskTables& t = *pl->disk;
+        const double2* F = reinterpret_cast<const double2*>(f);
+        double2* U = reinterpret_cast<double2*>(u);
+        if (space == CYL_SPACE_VALUE) {
+            transform_fwd(pl, f, pl->planesA.as<double2>());
+            F = pl->planesA.as<double2>();
+            U = pl->planesB.as<double2>();
+        }
+        {
+            Scope sc(pl, PH_ADI);
+            hip_check(launch_disk(F, U, pl->disk_lu.as<double>(), pl->disk_taps.as<double>(), g.m, g.n, g.nw,
+                                  t.rmax, t.rows[0], t.rows[1], pl->stream),
+                      "disk solve");
+        }
+        if (space == CYL_SPACE_VALUE) transform_inv(pl, pl->planesB.as<double2>(), u);
     });
 }
 

@@ -143,6 +143,11 @@ hipError_t adi_split_set_lds_limit(int np0, size_t bytes);
 // [p][n][m] (boundary.hip).
 hipError_t launch_trace_lift(const double* rface, const double* zface, const double* ra, const double* zb,
                              double* lift, int m, int n, int p, hipStream_t s);
+// Horizontal (disk) Poisson (disk.hip): U = disk solve of F, planes
+// [nw][n][m] complex, U not aliasing F; lu [nw][2][rmax][4] and taps
+// [2][rmax][5] as built by build_disk_tables; rows0/rows1: parity row counts.
+hipError_t launch_disk(const double2* F, double2* U, const double* lu, const double* taps, int m, int n,
+                       int nw, int rmax, int rows0, int rows1, hipStream_t s);
 // Zero the me x ne solution region (at xoff) of every listed block; me0, ne0
 // bound the block sizes.
 hipError_t launch_zero_blocks(const BlockDesc* blocks, int nblocks, int me0, int ne0, double* X,

@@ -831,4 +831,57 @@ DftTables build_dft_tables(int L, bool mixed) {
     return t;
 }
 
+// ----------------------------------------------------------------------------
+// horizontal (disk) Poisson tables
+// ----------------------------------------------------------------------------
+
+DiskTables build_disk_tables(const DirOps& ops, int nw) {
+    DiskTables t;
+    const int m = ops.n;
+    const Band R2tau = band_cut(ops.R2f, m - 2, m);
+    Band Rp[2];
+    for (int par = 0; par < 2; ++par) {
+        Rp[par] = band_parity(R2tau, par);
+        t.rows[par] = Rp[par].rows;
+        t.cols[par] = Rp[par].cols;
+        for (int i = 0; i < Rp[par].rows; ++i)
+            for (int j = 0; j < Rp[par].cols; ++j)
+                if ((j < i - 1 || j > i + 3) && Rp[par].get(i, j) != 0.0)
+                    throw std::logic_error("disk right side wider than its taps");
+    }
+    t.rmax = std::max(t.rows[0], t.rows[1]);
+    t.taps.assign(2 * static_cast<size_t>(t.rmax) * kDiskTaps, 0.0);
+    for (int par = 0; par < 2; ++par)
+        for (int i = 0; i < t.rows[par]; ++i)
+            for (int s = 0; s < kDiskTaps; ++s)
+                t.taps[(static_cast<size_t>(par) * t.rmax + i) * kDiskTaps + s] = Rp[par].get(i, i - 1 + s);
+    t.lu.assign(static_cast<size_t>(nw) * 2 * t.rmax * kDiskRec, 0.0);
+    for (int w = 0; w < nw; ++w) {
+        const Band Aw = band_axpby(1.0, ops.A0, -static_cast<double>(w) * w, ops.Cc);
+        for (int par = 0; par < 2; ++par) {
+            const Band A = band_parity(Aw, par);
+            const int nr = A.rows;
+            for (int i = 0; i < nr; ++i)
+                for (int j = 0; j < nr; ++j)
+                    if ((j < i - 1 || j > i + 2) && A.get(i, j) != 0.0)
+                        throw std::logic_error("disk operator wider than (1, 2)");
+            double* rec = &t.lu[((static_cast<size_t>(w) * 2 + par) * t.rmax) * kDiskRec];
+            long double u0p = 0, u1p = 0, u2p = 0;    // previous row of U: d, U(i,i+1), U(i,i+2)
+            for (int i = 0; i < nr; ++i) {
+                const long double l = i > 0 ? static_cast<long double>(A.get(i, i - 1)) / u0p : 0.0L;
+                const long double d = static_cast<long double>(A.get(i, i)) - l * u1p;
+                const long double e1 = static_cast<long double>(A.get(i, i + 1)) - l * u2p;
+                const long double e2 = static_cast<long double>(A.get(i, i + 2));
+                if (d == 0.0L) throw std::runtime_error("zero pivot in the disk operator");
+                rec[i * kDiskRec + 0] = static_cast<double>(l);
+                rec[i * kDiskRec + 1] = static_cast<double>(1.0L / d);
+                rec[i * kDiskRec + 2] = static_cast<double>(e1 / d);
+                rec[i * kDiskRec + 3] = static_cast<double>(e2 / d);
+                u0p = d; u1p = e1; u2p = e2;
+            }
+        }
+    }
+    return t;
+}
+
 }  // namespace cyl

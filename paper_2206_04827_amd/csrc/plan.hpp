@@ -58,6 +58,20 @@ void adi_shifts(double a, double b, double c, double d, int J, double* u, double
 double jacobi_dn_frac(double t, double kp);   // dn(t K(k), k), 0 <= t <= 1
 double ellip_K_from_kp(double kp);
 
+// Horizontal (disk) Poisson of Section 4 (Delta_h = nabla^2 - d_zz, diagonal
+// in theta and z): per z coefficient one tau system [A_w Q]_tau x = [R^2 C02 f]_tau
+// in r, split by r parity.  Per (wavenumber slot, parity), per parity row i:
+// lu[4] = (L_i of the unit lower factor, 1/d_i, U_(i,i+1)/d_i, U_(i,i+2)/d_i)
+// of the no-pivot LU (bandwidths 1 and 2 within a parity); per parity, per
+// row, taps[5] of [R^2 C02]_tau on the same-parity T coefficients i-1 .. i+3.
+constexpr int kDiskRec = 4, kDiskTaps = 5;
+struct DiskTables {
+    int rows[2] = {0, 0}, cols[2] = {0, 0}, rmax = 0;
+    std::vector<double> lu;     // [nw][2][rmax][kDiskRec]
+    std::vector<double> taps;   // [2][rmax][kDiskTaps]
+};
+DiskTables build_disk_tables(const DirOps& ops, int nw);
+
 constexpr int kMaxRadixPasses = 12;
 // Per-length DFT tables (complex length L; FFT length Nb = L when L factors
 // into the supported radices, else the power of two >= 2L - 1 of Bluestein).

@@ -82,6 +82,7 @@ def test_null_arguments_are_rejected(lib):
     assert lib.cyl_batch_destroy(None) == 1
     assert lib.cyl_plan_set_physical(None, 1) == 1
     assert lib.cyl_trace_lift(None, None, None, None) == 1
+    assert lib.cyl_disk_poisson_solve(None, 0, None, None) == 1
 
 
 def test_adi_parameter_validation():
