@@ -1213,7 +1213,9 @@ __global__ __launch_bounds__(256) void k_heat_rhs_batch(const HeatRhsItem* __res
         const int64_t e = base + c * 256;
         if (e >= it.total) break;
         double acc = it.Ec[e];
-        for (int b = 0; b < it.nb; ++b) acc += it.beta[b] * it.P[b][e];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)          // fixed bound: the item stays in registers
+            if (b < it.nb) acc += it.beta[b] * it.P[b][e];
         it.E[e] = acc;
     }
 }
