@@ -129,8 +129,11 @@ int cyl_poisson_solve(cyl_plan_t plan, int space, const double* f, const double*
  * other-parity part of f (rounding for physical forcing) is discarded.  The
  * residual ratio reported in cyl_solve_info still covers all of f.  Needs an
  * even n_theta (CYL_E_UNSUPPORTED otherwise: for odd n_theta theta + pi is no
- * grid angle and the sampled parities mix).  Applies to cyl_poisson_solve
- * only; heat handles solve all blocks. */
+ * grid angle and the sampled parities mix).  Heat handles created while the
+ * flag is set step the same way (BDF keeps the subspace): their initial state
+ * and forcing are taken as physical, and their steps solve and project the
+ * j = w (mod 2) blocks only; cyl_heat_grad_create and cyl_batch_create reject
+ * such handles with CYL_E_UNSUPPORTED. */
 int cyl_plan_set_physical(cyl_plan_t plan, int enable);
 
 /* Lift from boundary traces (non-homogeneous Dirichlet data given on the

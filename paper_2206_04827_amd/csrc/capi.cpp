@@ -165,6 +165,7 @@ struct cyl_heat_s {
     double beta[4] = {0, 0, 0, 0};
     DevMem P[4], Econst, Xt, lift, T0;
     bool has_lift = false;
+    bool physical = false; // steps solve the j = w (mod 2) blocks only (the plan's flag at creation)
     int head = 0;          // index of the newest history level
     long long steps = 0;
 };
@@ -1142,6 +1143,10 @@ int cyl_heat_create(cyl_heat_t* h, cyl_plan_t plan, double alpha, double dt, int
                                   pl->plane_of.as<int>(), geo.nw, geo.m, geo.n, pl->rhs, pl->stream),
                       "forcing rhs");
         }
+        H->physical = pl->physical;
+        if (H->physical)      // the skipped blocks' solutions are never written: zero them once
+            hip_check(launch_zero_blocks(H->setup->blocks_skip.as<BlockDesc>(), H->setup->n_skip, geo.me[0],
+                                         geo.ne[0], H->Xt.as<double>(), pl->stream), "zero blocks");
         H->head = 0;
         *h = H.release();
     });
@@ -1154,7 +1159,8 @@ int cyl_heat_step(cyl_heat_t h, int n_steps) {
         cyl_plan_s* pl = h->plan;
         const Geometry& g = pl->geo;
         Setup* s = h->setup.get();
-        const int nblk = static_cast<int>(s->hblocks.size());
+        const int nblk = h->physical ? s->n_phys : static_cast<int>(s->hblocks.size());
+        const BlockDesc* blocks = (h->physical ? s->blocks_phys : s->blocks).as<BlockDesc>();
         for (int st = 0; st < n_steps; ++st) {
             const double* P[4];
             for (int i = 0; i < h->order; ++i) P[i] = h->P[(h->head + i) % h->order].as<double>();
@@ -1163,12 +1169,12 @@ int cyl_heat_step(cyl_heat_t h, int n_steps) {
                 hip_check(launch_heat_rhs(pl->E.as<double>(), P, h->beta, h->order, h->Econst.as<double>(),
                                           g.etotal_elems, pl->stream), "heat rhs");
             }
-            adi_solve(pl, s, pl->E.as<double>(), h->Xt.as<double>());
+            adi_solve(pl, s, pl->E.as<double>(), h->Xt.as<double>(), h->physical);
             // the oldest slot becomes the newest: P_new = C~ Xt B~
             const int slot = (h->head + h->order - 1) % h->order;
             {
                 Scope sc(pl, PH_PROJ);
-                hip_check(launch_apply2(s->blocks.as<BlockDesc>(), nblk, g.me[0], g.ne[0], nullptr, 0.0,
+                hip_check(launch_apply2(blocks, nblk, g.me[0], g.ne[0], nullptr, 0.0,
                                         h->Xt.as<double>(), -1.0, 0.0, h->P[slot].as<double>(),
                                         pl->atab_proj.as<double>(), 0, pl->ztabA.as<double>(),
                                         pl->stream), "project");
@@ -1340,6 +1346,7 @@ int cyl_heat_grad_create(cyl_heat_grad_t* out, cyl_heat_t h, int n_steps, int ch
         if (checkpoint_every < 1) fail(CYL_E_INVALID_ARG, "checkpoint_every must be >= 1");
         if (h->order != 1) fail(CYL_E_UNSUPPORTED, "differentiation supports BDF1 only");
         if (h->has_lift) fail(CYL_E_UNSUPPORTED, "differentiation supports homogeneous Dirichlet data only");
+        if (h->physical) fail(CYL_E_UNSUPPORTED, "differentiation solves all parity blocks (physical heat handle)");
         cyl_plan_s* pl = h->plan;
         const Geometry& g = pl->geo;
         auto a = std::make_unique<cyl_heat_grad_s>();
@@ -1499,6 +1506,7 @@ int cyl_batch_create(cyl_batch_t* out, int count, const cyl_heat_t* heats, int f
             for (int j = 0; j < i; ++j)
                 if (heats[j] == heats[i]) fail(CYL_E_INVALID_ARG, "a heat handle appears twice");
             if (heats[i]->stream != heats[0]->stream) fail(CYL_E_INVALID_ARG, "member plans use different streams");
+            if (heats[i]->physical) fail(CYL_E_UNSUPPORTED, "batches step all parity blocks (physical heat handle)");
             B->heats.push_back(heats[i]);
         }
         B->user = heats[0]->stream;

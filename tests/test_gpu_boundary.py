@@ -122,3 +122,42 @@ def test_physical_needs_even_theta_count():
     with pytest.raises(cyl.CylError) as e:
         plan.set_physical(True)
     assert e.value.status == 2
+
+
+# ----------------------------------------------------------------------------
+# heat stepping on the physical-parity blocks
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n,p,order", [(24, 20, 8, 1), (21, 17, 6, 4), (130, 120, 4, 1)])
+def test_physical_heat_matches_oracle(m, n, p, order):
+    """Physical initial state and forcing: the fast path's BDF steps agree
+    with the oracle's full heat solve (one thread per line and split kernels)."""
+    need_gpu()
+    banner("physical heat m=%d n=%d p=%d bdf%d" % (m, n, p, order))
+    hist = [synth.physical_values(m, n, p, S + 150 + i) for i in range(order)]
+    g = synth.physical_values(m, n, p, S + 159)
+    plan = cyl.Plan(m, n, p)
+    plan.set_physical(True)
+    H = cyl.Heat(plan, [dev(x) for x in hist], dev(g), 0.8, 1e-3, order, 1e-12)
+    H.step(5)
+    got = host(H.read())
+    ref = pb.heat(hist, g, 0.8, 1e-3, 5, order=order)
+    assert_close(got, ref, TOL, "physical heat")
+    c = tr.forward(got)
+    mask = bd.physical_mask(m, p)
+    assert np.max(np.abs(np.where(mask, 0.0, c))) < 1e-13 * np.max(np.abs(c))
+
+
+def test_physical_heat_handles_are_rejected_by_batch_and_grad():
+    need_gpu()
+    m, n, p = 16, 14, 6
+    plan = cyl.Plan(m, n, p)
+    plan.set_physical(True)
+    T0 = dev(synth.physical_values(m, n, p, S + 160))
+    H = cyl.Heat(plan, [T0], torch.zeros_like(T0), 1.0, 1e-3, 1, 1e-12)
+    with pytest.raises(cyl.CylError) as e:
+        cyl.HeatGrad(H, 4, 2)
+    assert e.value.status == 2
+    with pytest.raises(cyl.CylError) as e:
+        cyl.Batch([H])
+    assert e.value.status == 2
