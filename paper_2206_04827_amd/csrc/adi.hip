@@ -34,6 +34,7 @@ constexpr int kRRec = 12;
 constexpr int kZRec = 8;
 constexpr int kRCouple = 3;   // record rows after a block's r records (5 x 5 coupling)
 constexpr int kZCouple = 2;   // record rows after a block's z records (3 x 3 coupling)
+constexpr int kResTileK = 128; // columns per LDS-staged residual tile (state in global memory)
 
 // ---------------------------------------------------------------------------
 // LDS-resident sweeps with a compile-time row stride LD (so every row offset
@@ -676,7 +677,8 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
                                                 const double* __restrict__ E, double* X,
                                                 const double* __restrict__ rtab,
                                                 const double* __restrict__ ztab,
-                                                const double* __restrict__ vmu, int accumulate) {
+                                                const double* __restrict__ vmu, int accumulate,
+                                                const ResArgs& res) {
     const int me = bd.me, ne = bd.ne, mp = bd.mp, np = bd.np, tr = bd.tr, tz = bd.tz;
     const int tid = threadIdx.x, nt = blockDim.x, L = nt >> 1;
     const int line = tid % L;
@@ -777,20 +779,106 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
         const double v = S[i * LD + k];
         Xb[idx] = accumulate ? Xb[idx] + v : v;
     }
+    if (res.R != nullptr) {
+        // R = E - (A X B + C X D) from the solution still held in S (the
+        // block is the whole parity problem: outside it X is zero), over
+        // tiles of 64 rows: a lane owns a row, a wave a run of columns along
+        // which the 6 x 4 window of X under the stencil slides; E is read one
+        // group of kRG columns ahead.  With the state in global memory each
+        // tile of X (and its halo) is first staged in LDS, whose records are
+        // no longer needed.
+        constexpr int kRG = 4;
+        constexpr int TK = kGS ? kResTileK : LD;
+        constexpr int TS = kResTileK + 3;
+        const int lane = tid & 63;
+        const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), nw = nt >> 6;
+        const double* at = res.atab + bd.w * res.a_wstride + (bd.pr ? res.me0 * 12 : 0);
+        const double* zt = res.ztabA + (bd.pz ? res.ne0 * 8 : 0);
+        const double* Eb = E + bd.eoff;
+        double* Rb = res.R + bd.eoff;
+        for (int i0 = 0; i0 < me; i0 += 64) {
+            for (int k0 = 0; k0 < ne; k0 += TK) {
+                const int kw = ne - k0 < TK ? ne - k0 : TK;
+                const int i = i0 + lane;
+                const int kc = (kw + nw - 1) / nw, kb = k0 + wv * kc;
+                const int ke = kb + kc < k0 + kw ? kb + kc : k0 + kw;
+                const bool act = i < me && kb < ke;
+                double a[12], x[6][4], ec[kRG], en[kRG];
+                // E of the first group and the row's records are requested
+                // before the tile is staged
+#pragma unroll
+                for (int q = 0; q < kRG; ++q)
+                    ec[q] = act && kb + q < ke ? Eb[static_cast<int64_t>(kb + q) * mp + i] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 12; ++q) a[q] = act ? at[i * 12 + q] : 0.0;
+                if (kGS) {
+                    __syncthreads();
+                    for (int idx = tid; idx < (64 + 5) * (kw + 3); idx += nt) {
+                        const int rr = idx / (kw + 3), cc = idx - rr * (kw + 3);
+                        const int r = i0 - 2 + rr, c = k0 - 1 + cc;
+                        sm[rr * TS + cc] = (r >= 0 && r < me && c >= 0 && c < ne) ? S[r * LD + c] : 0.0;
+                    }
+                    __syncthreads();
+                }
+                auto xv = [&](int r, int c) {
+                    if (kGS) return sm[(r - i0 + 2) * TS + (c - k0 + 1)];
+                    return (r >= 0 && r < me && c >= 0 && c < ne) ? S[r * LD + c] : 0.0;
+                };
+                if (!act) continue;
+#pragma unroll
+                for (int da = 0; da < 6; ++da)
+#pragma unroll
+                    for (int dl = 0; dl < 3; ++dl) x[da][dl + 1] = xv(i - 2 + da, kb - 1 + dl);
+                for (int kg = kb; kg < ke; kg += kRG) {
+#pragma unroll
+                    for (int q = 0; q < kRG; ++q)
+                        en[q] = kg + kRG + q < ke ? Eb[static_cast<int64_t>(kg + kRG + q) * mp + i] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < kRG; ++q) {
+                        const int k = kg + q;
+                        if (k >= ke) break;
+#pragma unroll
+                        for (int da = 0; da < 6; ++da) {
+#pragma unroll
+                            for (int dl = 0; dl < 3; ++dl) x[da][dl] = x[da][dl + 1];
+                            x[da][3] = xv(i - 2 + da, k + 2);
+                        }
+                        const double* zc = zt + k * 8;
+                        double sab = 0.0, scd = 0.0;
+#pragma unroll
+                        for (int da = 0; da < 6; ++da) {
+                            double xb = 0.0, xd = 0.0;
+#pragma unroll
+                            for (int dl = 0; dl < 4; ++dl) {
+                                xb += x[da][dl] * zc[dl];
+                                xd += x[da][dl] * zc[4 + dl];
+                            }
+                            sab += a[da] * xb;
+                            scd += a[6 + da] * xd;
+                        }
+                        Rb[static_cast<int64_t>(k) * mp + i] = ec[q] - sab - scd;
+                    }
+#pragma unroll
+                    for (int q = 0; q < kRG; ++q) ec[q] = en[q];
+                }
+            }
+        }
+    }
 }
 
 template <int NP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_adi_split(const BlockDesc* __restrict__ blocks, const double* __restrict__ E, double* X,
                  const double* __restrict__ rtab, const double* __restrict__ ztab,
-                 const double* __restrict__ vmu, int accumulate, const AdiPtrs* __restrict__ pp) {
+                 const double* __restrict__ vmu, int accumulate, const AdiPtrs* __restrict__ pp,
+                 ResArgs res) {
     extern __shared__ double sm[];
     const BlockDesc bd = blocks[blockIdx.x];
     if (pp != nullptr) {
         const AdiPtrs q = pp[bd.prob];
         E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
     }
-    adi_block_split<NP + 1, false>(sm, nullptr, bd, E, X, rtab, ztab, vmu, accumulate);
+    adi_block_split<NP + 1, false>(sm, nullptr, bd, E, X, rtab, ztab, vmu, accumulate, res);
 }
 
 // Blocks too large for LDS (n up to 514): split sweeps with the state in
@@ -802,7 +890,7 @@ __global__ __launch_bounds__(512) void k_adi_split_gs(const BlockDesc* __restric
                                                       const double* __restrict__ rtab,
                                                       const double* __restrict__ ztab,
                                                       const double* __restrict__ vmu, int accumulate,
-                                                      const AdiPtrs* __restrict__ pp) {
+                                                      const AdiPtrs* __restrict__ pp, ResArgs res) {
     extern __shared__ double sm[];
     const BlockDesc bd = blocks[blockIdx.x];
     if (pp != nullptr) {
@@ -810,7 +898,7 @@ __global__ __launch_bounds__(512) void k_adi_split_gs(const BlockDesc* __restric
         E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
     }
     adi_block_split<NP + 1, true>(sm, state + static_cast<int64_t>(blockIdx.x) * state_stride, bd, E, X, rtab,
-                                  ztab, vmu, accumulate);
+                                  ztab, vmu, accumulate, res);
 }
 
 // ---------------------------------------------------------------------------
@@ -1262,9 +1350,10 @@ hipError_t set_limit(size_t bytes) {
 template <int NP>
 hipError_t launch_split(const BlockDesc* blocks, int nblocks, int threads, const double* E,
                         double* X, const double* rtab, const double* ztab, const double* vmu,
-                        bool accumulate, size_t lds_bytes, hipStream_t s, const AdiPtrs* pp) {
+                        bool accumulate, size_t lds_bytes, hipStream_t s, const AdiPtrs* pp,
+                        const ResArgs& res) {
     hipLaunchKernelGGL(k_adi_split<NP>, dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
-                       rtab, ztab, vmu, accumulate ? 1 : 0, pp);
+                       rtab, ztab, vmu, accumulate ? 1 : 0, pp, res);
     return hipGetLastError();
 }
 
@@ -1272,15 +1361,21 @@ template <int NP>
 hipError_t launch_split_gs(const BlockDesc* blocks, int nblocks, int threads, const double* E, double* X,
                            double* state, int64_t state_stride, const double* rtab, const double* ztab,
                            const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
-                           const AdiPtrs* pp) {
+                           const AdiPtrs* pp, const ResArgs& res) {
     hipLaunchKernelGGL(k_adi_split_gs<NP>, dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X, state,
-                       state_stride, rtab, ztab, vmu, accumulate ? 1 : 0, pp);
+                       state_stride, rtab, ztab, vmu, accumulate ? 1 : 0, pp, res);
     return hipGetLastError();
 }
 
 template <int NP>
 hipError_t set_split_limit(size_t bytes) {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_split<NP>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+}
+
+template <int NP>
+hipError_t set_split_gs_limit(size_t bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_split_gs<NP>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
 
@@ -1316,10 +1411,11 @@ size_t adi_split_lds_bytes(int mp0, int np0) {
 hipError_t launch_adi_split(const BlockDesc* blocks, int nblocks, int threads, int np0,
                             const double* E, double* X, const double* rtab, const double* ztab,
                             const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
-                            const AdiPtrs* pp) {
+                            const AdiPtrs* pp, const ResArgs* res) {
     if (threads < 128 || threads > 256 || threads % 128 != 0) return hipErrorInvalidValue;
+    const ResArgs ra = res ? *res : ResArgs{nullptr, nullptr, nullptr, 0, 0, 0};
     switch (np0) {
-#define CYL_CASE(v) case v: return launch_split<v>(blocks, nblocks, threads, E, X, rtab, ztab, vmu, accumulate, lds_bytes, s, pp);
+#define CYL_CASE(v) case v: return launch_split<v>(blocks, nblocks, threads, E, X, rtab, ztab, vmu, accumulate, lds_bytes, s, pp, ra);
         CYL_NP_CASES(CYL_CASE)
 #undef CYL_CASE
         default: return hipErrorInvalidValue;
@@ -1329,11 +1425,12 @@ hipError_t launch_adi_split(const BlockDesc* blocks, int nblocks, int threads, i
 #define CYL_NP_GS_CASES(X) X(136) X(144) X(152) X(160) X(168) X(176) X(184) X(192) X(200) X(208) \
     X(216) X(224) X(232) X(240) X(248) X(256)
 
-size_t adi_split_gs_lds_bytes(int mp0, int np0, int lines) {
+size_t adi_split_gs_lds_bytes(int mp0, int np0, int lines, bool residual) {
     auto chunks = [](int x) { return static_cast<size_t>((x + 127) / 128 * 128); };
     const size_t doubles = chunks((mp0 + kRCouple) * kRRec) + chunks((np0 + kZCouple) * kZRec) +
                            5 * static_cast<size_t>(lines);
-    return doubles * sizeof(double);
+    const size_t tile = residual ? static_cast<size_t>(64 + 5) * (kResTileK + 3) : 0;   // residual epilogue
+    return std::max(doubles, tile) * sizeof(double);
 }
 
 int64_t adi_split_gs_state_stride(int mp0, int np0) {
@@ -1343,10 +1440,12 @@ int64_t adi_split_gs_state_stride(int mp0, int np0) {
 hipError_t launch_adi_split_gs(const BlockDesc* blocks, int nblocks, int threads, int np0,
                                const double* E, double* X, double* state, int64_t state_stride,
                                const double* rtab, const double* ztab, const double* vmu,
-                               bool accumulate, size_t lds_bytes, hipStream_t s, const AdiPtrs* pp) {
+                               bool accumulate, size_t lds_bytes, hipStream_t s, const AdiPtrs* pp,
+                               const ResArgs* res) {
     if (threads < 128 || threads > 512 || threads % 128 != 0) return hipErrorInvalidValue;
+    const ResArgs ra = res ? *res : ResArgs{nullptr, nullptr, nullptr, 0, 0, 0};
     switch (np0) {
-#define CYL_CASE(v) case v: return launch_split_gs<v>(blocks, nblocks, threads, E, X, state, state_stride, rtab, ztab, vmu, accumulate, lds_bytes, s, pp);
+#define CYL_CASE(v) case v: return launch_split_gs<v>(blocks, nblocks, threads, E, X, state, state_stride, rtab, ztab, vmu, accumulate, lds_bytes, s, pp, ra);
         CYL_NP_GS_CASES(CYL_CASE)
 #undef CYL_CASE
         default: return hipErrorInvalidValue;
@@ -1357,6 +1456,15 @@ hipError_t adi_split_set_lds_limit(int np0, size_t bytes) {
     switch (np0) {
 #define CYL_CASE(v) case v: return set_split_limit<v>(bytes);
         CYL_NP_CASES(CYL_CASE)
+#undef CYL_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t adi_split_gs_set_lds_limit(int np0, size_t bytes) {
+    switch (np0) {
+#define CYL_CASE(v) case v: return set_split_gs_limit<v>(bytes);
+        CYL_NP_GS_CASES(CYL_CASE)
 #undef CYL_CASE
         default: return hipErrorInvalidValue;
     }

@@ -143,6 +143,7 @@ struct cyl_plan_s {
     bool use_lds = false;
     bool adi_split = false;        // split-sweep kernel (two threads per line)
     bool split_gs = false;         //   with the block state in global memory
+    bool fused_res = false;        //   emitting the first pass's residual itself
     int64_t state_stride = 0;
     int adi_threads = 64;
     size_t lds_bytes = 0;
@@ -475,27 +476,34 @@ void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X, bool physica
     const Geometry& g = pl->geo;
     const int nblk = physical ? s->n_phys : static_cast<int>(s->hblocks.size());
     DevMem& blocks = physical ? s->blocks_phys : s->blocks;
+    const int64_t a_wstride = static_cast<int64_t>(g.me[0] + g.me[1]) * 12;
+    // two passes with split kernels: the first pass writes the residual of its
+    // own solution (no separate residual launch)
+    const bool fuse = pl->fused_res && s->passes == 2;
+    const ResArgs res{pl->R.as<double>(), s->atab.as<double>(), s->ztabA, a_wstride, g.me[0], g.ne[0]};
     for (int pass = 0; pass < s->passes; ++pass) {
         const double* rhs = E;
-        if (pass > 0) {
+        if (pass > 0 && fuse) {
+            rhs = pl->R.as<double>();
+        } else if (pass > 0) {
             Scope sc(pl, PH_RES);
             hip_check(launch_apply2(blocks.as<BlockDesc>(), nblk, g.me[0], g.ne[0], E, 1.0, X, 1.0, 1.0,
-                                    pl->R.as<double>(), s->atab.as<double>(),
-                                    static_cast<int64_t>(g.me[0] + g.me[1]) * 12,
+                                    pl->R.as<double>(), s->atab.as<double>(), a_wstride,
                                     s->ztabA, pl->stream), "residual");
             rhs = pl->R.as<double>();
         }
         Scope sc(pl, PH_ADI);
+        const ResArgs* rp = fuse && pass == 0 ? &res : nullptr;
         if (pl->adi_split && pl->split_gs)
             hip_check(launch_adi_split_gs(blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
                                           pl->state.as<double>(), pl->state_stride, s->rtab.as<double>(),
                                           s->ztab.as<double>(), s->vmu.as<double>(), pass > 0, pl->lds_bytes,
-                                          pl->stream),
+                                          pl->stream, nullptr, rp),
                       "adi");
         else if (pl->adi_split)
             hip_check(launch_adi_split(blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
                                        s->rtab.as<double>(), s->ztab.as<double>(), s->vmu.as<double>(),
-                                       pass > 0, pl->lds_bytes, pl->stream),
+                                       pass > 0, pl->lds_bytes, pl->stream, nullptr, rp),
                       "adi");
         else
             hip_check(launch_adi(blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
@@ -665,11 +673,18 @@ void build_plan(cyl_plan_t pl) {
         pl->adi_split = true;
         pl->split_gs = true;
         pl->adi_threads = 2 * lines;
-        pl->lds_bytes = adi_split_gs_lds_bytes(g.mp[0], g.np[0], lines);
+        pl->fused_res = env_int("CYLSPEC_ADI_FUSED_RES", 1) != 0;
+        pl->lds_bytes = adi_split_gs_lds_bytes(g.mp[0], g.np[0], lines, pl->fused_res);
+        if (pl->lds_bytes > 65536 && adi_split_gs_set_lds_limit(g.np[0], pl->lds_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            pl->fused_res = false;
+            pl->lds_bytes = adi_split_gs_lds_bytes(g.mp[0], g.np[0], lines, false);
+        }
         pl->state_stride = adi_split_gs_state_stride(g.mp[0], g.np[0]);
         pl->state.alloc(static_cast<size_t>(4 * g.nplanes) * pl->state_stride * sizeof(double));
         pl->use_lds = true;        // no HBM-state one-thread kernel
     }
+    if (pl->adi_split && !pl->split_gs) pl->fused_res = env_int("CYLSPEC_ADI_FUSED_RES", 1) != 0;
     if (!pl->use_lds) {
         pl->adi_threads = std::min(512, pl->adi_threads);
         pl->state.alloc(static_cast<size_t>(4 * g.nplanes) * pl->state_stride * sizeof(double));
@@ -752,7 +767,7 @@ std::vector<BatchLaunch> build_launches(const std::vector<BlockRef>& refs, int g
         } else if (l.kind == 3) {
             // the kernel's row stride is the group's np + 1: size every slot for
             // the group's largest mp at that stride
-            l.lds = adi_split_gs_lds_bytes(mp, l.np, l.threads / 2);
+            l.lds = adi_split_gs_lds_bytes(mp, l.np, l.threads / 2, false);
             l.state_stride = adi_split_gs_state_stride(mp, l.np);
             l.state = std::make_unique<DevMem>();
             l.state->alloc(static_cast<size_t>(l.nblocks) * l.state_stride * sizeof(double));

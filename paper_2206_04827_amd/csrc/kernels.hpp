@@ -42,6 +42,18 @@ struct BlockDesc {
     int64_t soff;            // offset of v_j - u_j values
 };
 
+// Residual emitted by the split ADI kernels after their last iteration
+// (R == nullptr: none): R = E - (A X B + C X D) of the block just solved, with
+// the records of launch_apply2 (atab rows of 12 per (w, r parity), w stride
+// a_wstride; ztabA columns of 8 per z parity), written in E-layout.
+struct ResArgs {
+    double* R;
+    const double* atab;
+    const double* ztabA;
+    int64_t a_wstride;
+    int me0, ne0;
+};
+
 // Per-problem pointers of a batched launch, indexed by BlockDesc::prob.  When a
 // launcher receives a table, the table's pointers replace the launcher's own.
 struct AdiPtrs {
@@ -120,7 +132,7 @@ hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, int np0
 hipError_t launch_adi_split(const BlockDesc* blocks, int nblocks, int threads, int np0,
                             const double* E, double* X, const double* rtab, const double* ztab,
                             const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
-                            const AdiPtrs* pp = nullptr);
+                            const AdiPtrs* pp = nullptr, const ResArgs* res = nullptr);
 // LDS bytes of the split kernel for padded block sizes mp0 x np0.
 size_t adi_split_lds_bytes(int mp0, int np0);
 // Split sweeps with the block state in global memory (np0 in 136..256, a
@@ -130,13 +142,15 @@ hipError_t launch_adi_split_gs(const BlockDesc* blocks, int nblocks, int threads
                                const double* E, double* X, double* state, int64_t state_stride,
                                const double* rtab, const double* ztab, const double* vmu,
                                bool accumulate, size_t lds_bytes, hipStream_t s,
-                               const AdiPtrs* pp = nullptr);
-size_t adi_split_gs_lds_bytes(int mp0, int np0, int lines);
+                               const AdiPtrs* pp = nullptr, const ResArgs* res = nullptr);
+// residual: room for the fused residual epilogue's staged tile
+size_t adi_split_gs_lds_bytes(int mp0, int np0, int lines, bool residual);
 int64_t adi_split_gs_state_stride(int mp0, int np0);
 
 // Raise the dynamic-LDS limit of the LDS-resident ADI kernels for width np0.
 hipError_t adi_set_lds_limit(int np0, size_t bytes);
 hipError_t adi_split_set_lds_limit(int np0, size_t bytes);
+hipError_t adi_split_gs_set_lds_limit(int np0, size_t bytes);
 
 // Coons lift of the doubled box's faces: rface [2][p][n] (r = -1, +1), zface
 // [2][p][m] (z = -1, +1), ra_j = (1 + r_j)/2, zb_k = (1 + z_k)/2 -> lift

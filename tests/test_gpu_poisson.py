@@ -134,6 +134,35 @@ def test_large_block_sizes_full_field(m, n, p):
     assert_close(u, v, TOL, "split vs one-thread kernel")
 
 
+def _with_env(env, fn):
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return fn()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("m,n,p", [(130, 120, 4), (290, 270, 3)])
+def test_fused_residual_matches_separate_launch(m, n, p):
+    """Two-pass solves: the split kernels' own residual of the first pass (LDS
+    and global block state) and the separate residual launch give the same
+    solution; both match the oracle."""
+    need_gpu()
+    banner("fused residual m=%d n=%d p=%d" % (m, n, p))
+    f = smooth_values(m, n, p, S + 41 + m)
+    fused = _with_env({"CYLSPEC_PASSES": "2"}, lambda: _solve_values(m, n, p, f))
+    sep = _with_env({"CYLSPEC_PASSES": "2", "CYLSPEC_ADI_FUSED_RES": "0"}, lambda: _solve_values(m, n, p, f))
+    rel = np.max(np.abs(fused - sep)) / np.max(np.abs(sep))
+    print("  fused vs separate rel max %.3e" % rel)
+    assert rel < 1e-13
+    assert_close(fused, pb.poisson(f), TOL, "fused residual")
+
+
 def test_non_finite_input_reports_not_converged():
     need_gpu()
     m, n, p = 10, 10, 4
