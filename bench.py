@@ -50,12 +50,19 @@ HBM_PEAK_GBS = 8000.0
 # formulation: r-pass 24 (banded product 11, E term 2, forward 4, backward 7),
 # z-pass 14 (forward 2, backward 5, banded product 7).
 ADI_FLOPS_PER_UNKNOWN_ITER = 38.0
-# HBM bytes per ADI launch at 256^3 from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-# (scaled by a 512 MiB copy: fetch x2.0, write x1.0), valid for the ADI source
-# whose SHA-256 starts with ADI_TRAFFIC_SHA, at ADI tolerance ADI_TRAFFIC_TOL
-# (the traffic scales with the iteration count); reported as null otherwise.
-ADI_TRAFFIC_BYTES_256 = 2.227e9
-ADI_TRAFFIC_SHA = "d6c61b10f5240ef4"
+# FP64 operations per unknown of the residual R = E - (A X B + C X D) that the
+# first pass's ADI launch forms when it is fused there: the 6 x 4 window of X
+# against a column of B and of D (48 FMA), the rows of A and C (12 FMA), two
+# subtractions.
+RESIDUAL_FLOPS_PER_UNKNOWN = 122.0
+# HBM bytes per ADI launch at 256^3 (mean of the two passes, the first also
+# forming the residual) from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by
+# an elementwise kernel reading and writing 512 MiB: fetch x2.0, write x1.0),
+# valid for the ADI source whose SHA-256 starts with ADI_TRAFFIC_SHA, at ADI
+# tolerance ADI_TRAFFIC_TOL (the traffic scales with the iteration count);
+# reported as null otherwise.
+ADI_TRAFFIC_BYTES_256 = 2.354e9
+ADI_TRAFFIC_SHA = "65c9f20be455780d"
 ADI_TRAFFIC_TOL = 1e-10
 
 
@@ -80,8 +87,9 @@ def parse():
     ap.add_argument("--cpu-modes", type=int, default=16,
                     help="wavenumbers the CPU oracle solves in its timed sample")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run one plain 512 MiB device-to-device copy (a known-size "
-                         "kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
+                    help="also run one plain elementwise kernel reading 512 MiB and writing "
+                         "512 MiB (a known-size kernel for scaling FETCH_SIZE / WRITE_SIZE "
+                         "counters)")
     return ap.parse_args()
 
 
@@ -283,7 +291,9 @@ def main():
     n_adi = max(1, prof["n_adi"])
     adi_ms = prof["ms_adi"] / n_adi
     passes = info["passes"]
-    flops_per_launch = ADI_FLOPS_PER_UNKNOWN_ITER * (m - 2) * (n - 2) * p * info["adi_iterations_mean"]
+    fused = bool(info["fused_residual"])
+    flops_per_launch = (m - 2) * (n - 2) * p * (ADI_FLOPS_PER_UNKNOWN_ITER * info["adi_iterations_mean"] +
+                                                (RESIDUAL_FLOPS_PER_UNKNOWN / passes if fused else 0.0))
     achieved = flops_per_launch / (adi_ms * 1e-3) / 1e12
     import hashlib
     src = os.path.join(ROOT, "paper_2206_04827_amd", "csrc", "adi.hip")
@@ -293,7 +303,8 @@ def main():
                                          and args.tol == ADI_TRAFFIC_TOL) else None)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": "k_adi_split (one ADI pass over all parity blocks)",
+                "kernel": "k_adi_split (one ADI pass over all parity blocks%s)" %
+                          (", the first also forming the residual" if fused else ""),
                 "avg_launch_ms": round(adi_ms, 4), "launches": n_adi}
     phases = {k[3:]: round(prof[k] / args.steps, 4) for k in prof if k.startswith("ms_")}
 
@@ -402,7 +413,8 @@ def main():
     if args.calibrate_copy:
         a = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.cuda.synchronize()
+        torch.add(a, 1.0, out=b)           # one elementwise kernel: reads a, writes b
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = a.numel() * 8
 

@@ -66,7 +66,8 @@ typedef struct {
     int J_max;          /* most ADI iterations of any mode (per pass)        */
     int J_min;          /* fewest ADI iterations of any mode (per pass)      */
     int passes;         /* 1, or 2 when a residual-correction pass was run   */
-    int reserved;
+    int fused_residual; /* 1: the first pass's ADI launch also formed the
+                           residual for the second (no separate launch)      */
     double resid_ratio;
     double adi_iterations_mean; /* mean J over real mode planes, per pass   */
 } cyl_solve_info;

@@ -45,7 +45,7 @@ class CylError(RuntimeError):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("J_max", ctypes.c_int), ("J_min", ctypes.c_int), ("passes", ctypes.c_int),
-                ("reserved", ctypes.c_int), ("resid_ratio", ctypes.c_double),
+                ("fused_residual", ctypes.c_int), ("resid_ratio", ctypes.c_double),
                 ("adi_iterations_mean", ctypes.c_double)]
 
 

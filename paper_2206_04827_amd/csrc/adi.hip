@@ -36,6 +36,17 @@ constexpr int kRCouple = 3;   // record rows after a block's r records (5 x 5 co
 constexpr int kZCouple = 2;   // record rows after a block's z records (3 x 3 coupling)
 constexpr int kResTileK = 128; // columns per LDS-staged residual tile (state in global memory)
 
+// Pointers that may come from memory (the per-problem tables of a batch) are
+// generic, and generic pointers compile to flat accesses, which also count
+// against the LDS wait counter: every LDS wait then drains the outstanding
+// global loads as well.  Rebuilt from their integer values as global-space
+// pointers they compile to global accesses.
+template <typename T>
+__device__ __forceinline__ T* as_global(T* p) {
+    using G = __attribute__((address_space(1))) T*;
+    return (T*)(G)(reinterpret_cast<uintptr_t>(p));
+}
+
 // ---------------------------------------------------------------------------
 // LDS-resident sweeps with a compile-time row stride LD (so every row offset
 // within a group is an instruction immediate).
@@ -781,86 +792,115 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
     }
     if (res.R != nullptr) {
         // R = E - (A X B + C X D) from the solution still held in S (the
-        // block is the whole parity problem: outside it X is zero), over
-        // tiles of 64 rows: a lane owns a row, a wave a run of columns along
-        // which the 6 x 4 window of X under the stencil slides; E is read one
-        // group of kRG columns ahead.  With the state in global memory each
-        // tile of X (and its halo) is first staged in LDS, whose records are
-        // no longer needed.
-        constexpr int kRG = 4;
+        // block is the whole parity problem: outside it X is zero).  Tiles of
+        // 64 rows by TK columns; a lane owns a row, a wave a run of columns
+        // taken in groups of kRG, along which the 6 x 4 window of X under the
+        // stencil slides.  The work is one flat sequence of (tile, group)
+        // items, the same for every thread, and E of the next item is
+        // requested before the current one is computed (one wave per SIMD
+        // leaves nothing else to hide the latency).  With the state in global
+        // memory each tile of X and its halo is first staged in LDS, whose
+        // records are no longer needed.
+        constexpr int kRG = 16;
         constexpr int TK = kGS ? kResTileK : LD;
         constexpr int TS = kResTileK + 3;
         const int lane = tid & 63;
         const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), nw = nt >> 6;
         const double* at = res.atab + bd.w * res.a_wstride + (bd.pr ? res.me0 * 12 : 0);
         const double* zt = res.ztabA + (bd.pz ? res.ne0 * 8 : 0);
-        const double* Eb = E + bd.eoff;
-        double* Rb = res.R + bd.eoff;
-        for (int i0 = 0; i0 < me; i0 += 64) {
-            for (int k0 = 0; k0 < ne; k0 += TK) {
-                const int kw = ne - k0 < TK ? ne - k0 : TK;
-                const int i = i0 + lane;
-                const int kc = (kw + nw - 1) / nw, kb = k0 + wv * kc;
-                const int ke = kb + kc < k0 + kw ? kb + kc : k0 + kw;
-                const bool act = i < me && kb < ke;
-                double a[12], x[6][4], ec[kRG], en[kRG];
-                // E of the first group and the row's records are requested
-                // before the tile is staged
+        const double* Eb = as_global(E) + bd.eoff;
+        double* Rb = as_global(res.R) + bd.eoff;
+        const int ntk = (ne + TK - 1) / TK;
+        const int kcmax = ((ne < TK ? ne : TK) + nw - 1) / nw;
+        const int ng = (kcmax + kRG - 1) / kRG;
+        const int items = ((me + 63) / 64) * ntk * ng;
+        // item t: rows i0 .. i0+63, tile columns k0 .. k0+kw-1; this wave's
+        // columns kb .. ke-1 of the tile, this group's kg .. kg+kRG-1
+        struct Item { int i0, k0, kw, kb, ke, kg; };
+        auto item = [&](int t) {
+            Item r;
+            const int g = t % ng, tile = t / ng;
+            r.i0 = (tile / ntk) * 64;
+            r.k0 = (tile % ntk) * TK;
+            r.kw = ne - r.k0 < TK ? ne - r.k0 : TK;
+            const int kc = (r.kw + nw - 1) / nw;
+            r.kb = r.k0 + wv * kc;
+            r.ke = r.kb + kc < r.k0 + r.kw ? r.kb + kc : r.k0 + r.kw;
+            r.kg = r.kb + g * kRG;
+            return r;
+        };
+        double en[kRG];
+        auto load_e = [&](int t) {
+            const Item c = item(t);
+            const int i = c.i0 + lane;
 #pragma unroll
-                for (int q = 0; q < kRG; ++q)
-                    ec[q] = act && kb + q < ke ? Eb[static_cast<int64_t>(kb + q) * mp + i] : 0.0;
+            for (int q = 0; q < kRG; ++q)
+                en[q] = i < me && c.kg + q < c.ke ? Eb[static_cast<int64_t>(c.kg + q) * mp + i] : 0.0;
+        };
+        // the block's row and column records go to LDS (read as vector loads,
+        // each use would wait for the whole memory queue, prefetches included)
+        double* as = kGS ? sm + (64 + 5) * TS : RCs;
+        double* zs = kGS ? as + 12 * mp : ZCs;
+        for (int idx = tid; idx < me * 12; idx += nt) as[idx] = at[idx];
+        for (int idx = tid; idx < ne * 8; idx += nt) zs[idx] = zt[idx];
+        __syncthreads();
+        double a[12], x[6][4];
+        if (items > 0) load_e(0);
+        for (int t = 0; t < items; ++t) {
+            const Item c = item(t);
+            const int i = c.i0 + lane;
+            double ec[kRG];
 #pragma unroll
-                for (int q = 0; q < 12; ++q) a[q] = act ? at[i * 12 + q] : 0.0;
+            for (int q = 0; q < kRG; ++q) ec[q] = en[q];
+            if (t + 1 < items) load_e(t + 1);
+            auto xv = [&](int r, int col) {
+                if (kGS) return sm[(r - c.i0 + 2) * TS + (col - c.k0 + 1)];
+                return (r >= 0 && r < me && col >= 0 && col < ne) ? S[r * LD + col] : 0.0;
+            };
+            if (c.kg == c.kb) {                 // first group of a tile
                 if (kGS) {
                     __syncthreads();
-                    for (int idx = tid; idx < (64 + 5) * (kw + 3); idx += nt) {
-                        const int rr = idx / (kw + 3), cc = idx - rr * (kw + 3);
-                        const int r = i0 - 2 + rr, c = k0 - 1 + cc;
-                        sm[rr * TS + cc] = (r >= 0 && r < me && c >= 0 && c < ne) ? S[r * LD + c] : 0.0;
+                    for (int idx = tid; idx < (64 + 5) * (c.kw + 3); idx += nt) {
+                        const int rr = idx / (c.kw + 3), cc = idx - rr * (c.kw + 3);
+                        const int r = c.i0 - 2 + rr, col = c.k0 - 1 + cc;
+                        sm[rr * TS + cc] = (r >= 0 && r < me && col >= 0 && col < ne) ? S[r * LD + col] : 0.0;
                     }
                     __syncthreads();
                 }
-                auto xv = [&](int r, int c) {
-                    if (kGS) return sm[(r - i0 + 2) * TS + (c - k0 + 1)];
-                    return (r >= 0 && r < me && c >= 0 && c < ne) ? S[r * LD + c] : 0.0;
-                };
-                if (!act) continue;
+                if (i < me && c.kb < c.ke) {
 #pragma unroll
-                for (int da = 0; da < 6; ++da)
+                    for (int q = 0; q < 12; ++q) a[q] = as[i * 12 + q];
 #pragma unroll
-                    for (int dl = 0; dl < 3; ++dl) x[da][dl + 1] = xv(i - 2 + da, kb - 1 + dl);
-                for (int kg = kb; kg < ke; kg += kRG) {
+                    for (int da = 0; da < 6; ++da)
 #pragma unroll
-                    for (int q = 0; q < kRG; ++q)
-                        en[q] = kg + kRG + q < ke ? Eb[static_cast<int64_t>(kg + kRG + q) * mp + i] : 0.0;
-#pragma unroll
-                    for (int q = 0; q < kRG; ++q) {
-                        const int k = kg + q;
-                        if (k >= ke) break;
-#pragma unroll
-                        for (int da = 0; da < 6; ++da) {
-#pragma unroll
-                            for (int dl = 0; dl < 3; ++dl) x[da][dl] = x[da][dl + 1];
-                            x[da][3] = xv(i - 2 + da, k + 2);
-                        }
-                        const double* zc = zt + k * 8;
-                        double sab = 0.0, scd = 0.0;
-#pragma unroll
-                        for (int da = 0; da < 6; ++da) {
-                            double xb = 0.0, xd = 0.0;
-#pragma unroll
-                            for (int dl = 0; dl < 4; ++dl) {
-                                xb += x[da][dl] * zc[dl];
-                                xd += x[da][dl] * zc[4 + dl];
-                            }
-                            sab += a[da] * xb;
-                            scd += a[6 + da] * xd;
-                        }
-                        Rb[static_cast<int64_t>(k) * mp + i] = ec[q] - sab - scd;
-                    }
-#pragma unroll
-                    for (int q = 0; q < kRG; ++q) ec[q] = en[q];
+                        for (int dl = 0; dl < 3; ++dl) x[da][dl + 1] = xv(i - 2 + da, c.kb - 1 + dl);
                 }
+            }
+            if (i >= me || c.kg >= c.ke) continue;
+#pragma unroll
+            for (int q = 0; q < kRG; ++q) {
+                const int k = c.kg + q;
+                if (k >= c.ke) break;
+#pragma unroll
+                for (int da = 0; da < 6; ++da) {
+#pragma unroll
+                    for (int dl = 0; dl < 3; ++dl) x[da][dl] = x[da][dl + 1];
+                    x[da][3] = xv(i - 2 + da, k + 2);
+                }
+                const double* zc = zs + k * 8;
+                double sab = 0.0, scd = 0.0;
+#pragma unroll
+                for (int da = 0; da < 6; ++da) {
+                    double xb = 0.0, xd = 0.0;
+#pragma unroll
+                    for (int dl = 0; dl < 4; ++dl) {
+                        xb += x[da][dl] * zc[dl];
+                        xd += x[da][dl] * zc[4 + dl];
+                    }
+                    sab += a[da] * xb;
+                    scd += a[6 + da] * xd;
+                }
+                Rb[static_cast<int64_t>(k) * mp + i] = ec[q] - sab - scd;
             }
         }
     }
@@ -1337,7 +1377,7 @@ hipError_t launch_lds(const BlockDesc* blocks, int nblocks, int threads, const d
                       double* X, const double* rtab, const double* ztab, const double* vmu,
                       bool accumulate, size_t lds_bytes, hipStream_t s, const AdiPtrs* pp) {
     hipLaunchKernelGGL(k_adi_lds<NP>, dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
-                       rtab, ztab, vmu, accumulate ? 1 : 0, pp);
+                           rtab, ztab, vmu, accumulate ? 1 : 0, pp);
     return hipGetLastError();
 }
 
@@ -1353,7 +1393,7 @@ hipError_t launch_split(const BlockDesc* blocks, int nblocks, int threads, const
                         bool accumulate, size_t lds_bytes, hipStream_t s, const AdiPtrs* pp,
                         const ResArgs& res) {
     hipLaunchKernelGGL(k_adi_split<NP>, dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
-                       rtab, ztab, vmu, accumulate ? 1 : 0, pp, res);
+                           rtab, ztab, vmu, accumulate ? 1 : 0, pp, res);
     return hipGetLastError();
 }
 
@@ -1362,8 +1402,8 @@ hipError_t launch_split_gs(const BlockDesc* blocks, int nblocks, int threads, co
                            double* state, int64_t state_stride, const double* rtab, const double* ztab,
                            const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
                            const AdiPtrs* pp, const ResArgs& res) {
-    hipLaunchKernelGGL(k_adi_split_gs<NP>, dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X, state,
-                       state_stride, rtab, ztab, vmu, accumulate ? 1 : 0, pp, res);
+    hipLaunchKernelGGL(k_adi_split_gs<NP>, dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
+                           state, state_stride, rtab, ztab, vmu, accumulate ? 1 : 0, pp, res);
     return hipGetLastError();
 }
 
@@ -1397,7 +1437,7 @@ hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, int np0
         }
     }
     hipLaunchKernelGGL(k_adi_global, dim3(nblocks), dim3(threads), 0, s, blocks, E, X, state,
-                       state_stride, rtab, ztab, vmu, accumulate ? 1 : 0, pp);
+                           state_stride, rtab, ztab, vmu, accumulate ? 1 : 0, pp);
     return hipGetLastError();
 }
 
@@ -1429,7 +1469,9 @@ size_t adi_split_gs_lds_bytes(int mp0, int np0, int lines, bool residual) {
     auto chunks = [](int x) { return static_cast<size_t>((x + 127) / 128 * 128); };
     const size_t doubles = chunks((mp0 + kRCouple) * kRRec) + chunks((np0 + kZCouple) * kZRec) +
                            5 * static_cast<size_t>(lines);
-    const size_t tile = residual ? static_cast<size_t>(64 + 5) * (kResTileK + 3) : 0;   // residual epilogue
+    // residual epilogue: staged tile of X, then the row and column records
+    const size_t tile = residual ? static_cast<size_t>(64 + 5) * (kResTileK + 3) + 12 * static_cast<size_t>(mp0) +
+                                       8 * static_cast<size_t>(np0) : 0;
     return std::max(doubles, tile) * sizeof(double);
 }
 

@@ -143,7 +143,9 @@ struct cyl_plan_s {
     bool use_lds = false;
     bool adi_split = false;        // split-sweep kernel (two threads per line)
     bool split_gs = false;         //   with the block state in global memory
-    bool fused_res = false;        //   emitting the first pass's residual itself
+    int fused_res = 0;             //   emitting the first pass's residual itself (0 never,
+                                   //   1 with enough blocks per compute unit, 2 always)
+    int num_cus = 0;               // compute units of the device
     int64_t state_stride = 0;
     int adi_threads = 64;
     size_t lds_bytes = 0;
@@ -470,6 +472,17 @@ void transform_inv_adjoint(cyl_plan_t pl, const double* values, double* tmp, dou
     hip_check(launch_scale_planes(coeffs, g.m, g.n, g.p, 1, pl->stream), "scale planes");
 }
 
+// Two passes with split kernels: the first pass writes the residual of its
+// own solution (no separate residual launch).  Every round of resident blocks
+// then ends in a burst of E and R traffic; measured, this pays only with at
+// least four blocks per compute unit (one block per unit fits in LDS), the
+// separate full-occupancy launch otherwise.
+bool fuse_residual(const cyl_plan_s* pl, const Setup* s, bool physical) {
+    const int nblk = physical ? s->n_phys : static_cast<int>(s->hblocks.size());
+    return s->passes == 2 && (pl->fused_res == 2 ||
+                              (pl->fused_res == 1 && pl->num_cus > 0 && nblk >= 4 * pl->num_cus));
+}
+
 // ADI solve of all blocks (physical: the j = w (mod 2) blocks only):
 // X <- solution of A X B + C X D = E (setup pencil).
 void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X, bool physical = false) {
@@ -477,9 +490,7 @@ void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X, bool physica
     const int nblk = physical ? s->n_phys : static_cast<int>(s->hblocks.size());
     DevMem& blocks = physical ? s->blocks_phys : s->blocks;
     const int64_t a_wstride = static_cast<int64_t>(g.me[0] + g.me[1]) * 12;
-    // two passes with split kernels: the first pass writes the residual of its
-    // own solution (no separate residual launch)
-    const bool fuse = pl->fused_res && s->passes == 2;
+    const bool fuse = fuse_residual(pl, s, physical);
     const ResArgs res{pl->R.as<double>(), s->atab.as<double>(), s->ztabA, a_wstride, g.me[0], g.ne[0]};
     for (int pass = 0; pass < s->passes; ++pass) {
         const double* rhs = E;
@@ -534,7 +545,7 @@ void check_residual(cyl_plan_t pl, Setup* s, const double* E, const double* X, d
     info->J_max = s->h.J_max;
     info->J_min = s->h.J_min;
     info->passes = s->passes;
-    info->reserved = 0;
+    info->fused_residual = fuse_residual(pl, s, pl->physical) ? 1 : 0;
     info->adi_iterations_mean = s->h.J_mean;
     info->resid_ratio = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
     const double lim = 1e3 * std::max(eps, 1e-12);
@@ -642,6 +653,8 @@ void build_plan(cyl_plan_t pl) {
     int max_lds_sm = 0;
     if (hipDeviceGetAttribute(&max_lds_sm, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess)
         max_lds = std::max(max_lds, max_lds_sm);
+    if (hipDeviceGetAttribute(&pl->num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        pl->num_cus = 0;
     const int mode = env_int("CYLSPEC_ADI_GLOBAL", 0);
     pl->use_lds = mode == 0 && pl->adi_threads <= 256 && g.np[0] <= 128 &&
                   pl->lds_bytes <= static_cast<size_t>(max_lds);
@@ -673,18 +686,18 @@ void build_plan(cyl_plan_t pl) {
         pl->adi_split = true;
         pl->split_gs = true;
         pl->adi_threads = 2 * lines;
-        pl->fused_res = env_int("CYLSPEC_ADI_FUSED_RES", 1) != 0;
-        pl->lds_bytes = adi_split_gs_lds_bytes(g.mp[0], g.np[0], lines, pl->fused_res);
+        pl->fused_res = env_int("CYLSPEC_ADI_FUSED_RES", 1);
+        pl->lds_bytes = adi_split_gs_lds_bytes(g.mp[0], g.np[0], lines, pl->fused_res != 0);
         if (pl->lds_bytes > 65536 && adi_split_gs_set_lds_limit(g.np[0], pl->lds_bytes) != hipSuccess) {
             (void)hipGetLastError();
-            pl->fused_res = false;
+            pl->fused_res = 0;
             pl->lds_bytes = adi_split_gs_lds_bytes(g.mp[0], g.np[0], lines, false);
         }
         pl->state_stride = adi_split_gs_state_stride(g.mp[0], g.np[0]);
         pl->state.alloc(static_cast<size_t>(4 * g.nplanes) * pl->state_stride * sizeof(double));
         pl->use_lds = true;        // no HBM-state one-thread kernel
     }
-    if (pl->adi_split && !pl->split_gs) pl->fused_res = env_int("CYLSPEC_ADI_FUSED_RES", 1) != 0;
+    if (pl->adi_split && !pl->split_gs) pl->fused_res = env_int("CYLSPEC_ADI_FUSED_RES", 1);
     if (!pl->use_lds) {
         pl->adi_threads = std::min(512, pl->adi_threads);
         pl->state.alloc(static_cast<size_t>(4 * g.nplanes) * pl->state_stride * sizeof(double));

@@ -81,6 +81,31 @@ def test_gradients_match_oracle(m, n, p, steps, every):
     H.close()
 
 
+def test_gradients_with_fused_residual(monkeypatch):
+    """Two passes on the split kernels, each first pass writing its own
+    residual (forced here; chosen by itself only with several blocks per
+    compute unit): the forward and transposed heat solves agree with the
+    oracle."""
+    need_gpu()
+    monkeypatch.setenv("CYLSPEC_PASSES", "2")
+    monkeypatch.setenv("CYLSPEC_ADI_FUSED_RES", "2")
+    m, n, p, steps, every = 40, 36, 6, 4, 2
+    banner("heat grad fused residual %dx%dx%d" % (m, n, p))
+    alpha, h = 0.8, 1e-2
+    T0 = smooth_values(m, n, p, S + 75)
+    g = smooth_values(m, n, p, S + 76)
+    Tt = smooth_values(m, n, p, S + 77)
+    plan = cyl.Plan(m, n, p)
+    H, G, TN, T0b, gb, ab = _run(plan, T0, g, Tt, alpha, h, steps, every)
+    ref = ad.heat_bdf1_grad(T0, g, Tt, alpha, h, steps)
+    assert_close(TN, ref["T_final"], TOL, "T_N")
+    assert_close(T0b, ref["T0_bar"], TOL, "dL/dT0")
+    assert_close(gb, ref["g_bar"], TOL, "dL/dg")
+    assert abs(ab - ref["alpha_bar"]) <= TOL * abs(ref["alpha_bar"])
+    G.close()
+    H.close()
+
+
 def test_gradients_coefficient_space():
     need_gpu()
     m, n, p, steps, every = 16, 14, 6, 4, 3
