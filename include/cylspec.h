@@ -38,6 +38,8 @@
 #ifndef CYLSPEC_H
 #define CYLSPEC_H
 
+#include <stdint.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -254,6 +256,21 @@ int cyl_adi_parameters(int n_r, int n_z, int w, double kappa_alpha, double adi_t
 int cyl_plan_set_profiling(cyl_plan_t plan, int enable);
 /* Synchronise, return and reset the accumulated per-phase device times. */
 int cyl_plan_get_profile(cyl_plan_t plan, cyl_profile* out);
+
+/* Device peak check (measurement support, not a step of the method): the
+ * rates roofline fractions are quoted against, measured on this device.  On
+ * hip_stream (a hipStream_t, NULL = the default stream) it times one warm-up
+ * and then `reps` launches (1..1000) of each check with HIP events and keeps
+ * the fastest:
+ *   fp64_tflops: independent FP64 FMA chains in every lane of 8 workgroups
+ *     of 256 lanes per compute unit, 2 operations per FMA;
+ *   copy_gbs: a streaming copy dst[i] = src[i] of n doubles (device buffers,
+ *     16-byte aligned, not overlapping, n > 0), 16 n bytes moved per launch.
+ * Either output may be NULL to skip that check (src, dst and n are then
+ * unused by it).  Synchronises the stream; allocates nothing; dst is
+ * overwritten by the copy. */
+int cyl_device_peaks(void* hip_stream, const double* src, double* dst, int64_t n, int reps,
+                     double* fp64_tflops, double* copy_gbs);
 
 const char* cyl_status_string(int status);
 const char* cyl_last_error(void);

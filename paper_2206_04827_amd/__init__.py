@@ -31,7 +31,7 @@ EXPORTS = ["cyl_plan_create", "cyl_plan_destroy", "cyl_transform_fwd", "cyl_tran
            "cyl_transform_fwd_adjoint", "cyl_transform_inv_adjoint", "cyl_heat_grad_create",
            "cyl_heat_grad_forward", "cyl_heat_grad_backward", "cyl_heat_grad_destroy",
            "cyl_batch_create", "cyl_batch_step", "cyl_batch_describe", "cyl_batch_destroy",
-           "cyl_plan_set_physical", "cyl_trace_lift", "cyl_disk_poisson_solve"]
+           "cyl_plan_set_physical", "cyl_trace_lift", "cyl_disk_poisson_solve", "cyl_device_peaks"]
 
 CYL_BATCH_NO_GRAPH = 1
 CYL_BATCH_NO_TUNE = 2
@@ -100,6 +100,7 @@ def load():
         "cyl_plan_set_physical": [P, I],
         "cyl_trace_lift": [P, P, P, P],
         "cyl_disk_poisson_solve": [P, I, P, P],
+        "cyl_device_peaks": [P, P, P, ctypes.c_int64, I, ctypes.POINTER(D), ctypes.POINTER(D)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -131,6 +132,18 @@ def adi_parameters(n_r, n_z, w, kappa_alpha=0.0, adi_tol=1e-12, cap=512):
     v = (ctypes.c_double * cap)()
     _check(lib.cyl_adi_parameters(n_r, n_z, w, kappa_alpha, adi_tol, b4, ctypes.byref(J), u, v, cap))
     return {"bounds": list(b4), "J": J.value, "u": list(u[:J.value]), "v": list(v[:J.value])}
+
+
+def device_peaks(n=1 << 26, reps=5, stream=None):
+    """Measured FP64 FMA rate (TFLOP/s) and streaming-copy bandwidth (GB/s) of
+    the current device (the copy moves 2 x 8 n bytes per launch)."""
+    lib = load()
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    tf, gb = ctypes.c_double(), ctypes.c_double()
+    s = ctypes.c_void_p(stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream)
+    _check(lib.cyl_device_peaks(s, _ptr(src), _ptr(dst), n, reps, ctypes.byref(tf), ctypes.byref(gb)))
+    return {"fp64_tflops": tf.value, "copy_gbs": gb.value, "copy_bytes": 16 * n}
 
 
 class Plan:

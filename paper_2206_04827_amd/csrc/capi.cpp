@@ -1297,6 +1297,60 @@ int cyl_disk_poisson_solve(cyl_plan_t plan, int space, const double* f, double* 
     });
 }
 
+int cyl_device_peaks(void* hip_stream, const double* src, double* dst, int64_t n, int reps,
+                     double* fp64_tflops, double* copy_gbs) {
+    return guarded([&] {
+        if (reps < 1 || reps > 1000) fail(CYL_E_INVALID_ARG, "reps must lie in [1, 1000]");
+        if (copy_gbs) {
+            if (!src || !dst || n <= 0) fail(CYL_E_INVALID_ARG, "the copy needs src, dst and n > 0");
+            if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+                fail(CYL_E_INVALID_ARG, "src and dst must be 16-byte aligned");
+            if (src < dst + n && dst < src + n) fail(CYL_E_INVALID_ARG, "src and dst overlap");
+        }
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        int dev = 0, cus = 0;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+        struct Events {
+            hipEvent_t a = nullptr, b = nullptr;
+            ~Events() {
+                if (a) (void)hipEventDestroy(a);
+                if (b) (void)hipEventDestroy(b);
+            }
+        } ev;
+        hip_check(hipEventCreate(&ev.a), "event");
+        hip_check(hipEventCreate(&ev.b), "event");
+        // one warm-up launch, then the fastest of reps timed launches (ms)
+        auto best_ms = [&](auto&& launch) {
+            launch();
+            float best = 0.0f;
+            for (int r = 0; r < reps; ++r) {
+                hip_check(hipEventRecord(ev.a, s), "event record");
+                launch();
+                hip_check(hipEventRecord(ev.b, s), "event record");
+                hip_check(hipEventSynchronize(ev.b), "event sync");
+                float ms = 0.0f;
+                hip_check(hipEventElapsedTime(&ms, ev.a, ev.b), "elapsed");
+                if (r == 0 || ms < best) best = ms;
+            }
+            return static_cast<double>(best);
+        };
+        if (fp64_tflops) {
+            double flops = 0.0;
+            const double ms = best_ms([&] {
+                hip_check(launch_fma_peak(dst, 8 * cus, 4096, s, &flops), "fma peak");
+            });
+            *fp64_tflops = flops / (ms * 1e-3) / 1e12;
+        }
+        if (copy_gbs) {
+            const double ms = best_ms([&] {
+                hip_check(launch_copy_peak(src, dst, n, 16 * cus, s), "copy peak");
+            });
+            *copy_gbs = 2.0 * 8.0 * static_cast<double>(n) / (ms * 1e-3) / 1e9;
+        }
+    });
+}
+
 int cyl_plan_set_physical(cyl_plan_t plan, int enable) {
     return guarded([&] {
         if (!plan) fail(CYL_E_INVALID_ARG, "plan is NULL");

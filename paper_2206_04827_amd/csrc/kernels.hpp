@@ -162,6 +162,12 @@ hipError_t launch_trace_lift(const double* rface, const double* zface, const dou
 // [2][rmax][5] as built by build_disk_tables; rows0/rows1: parity row counts.
 hipError_t launch_disk(const double2* F, double2* U, const double* lu, const double* taps, int m, int n,
                        int nw, int rmax, int rows0, int rows1, hipStream_t s);
+// Device peak checks (peaks.hip).  launch_fma_peak: `blocks` workgroups of
+// 256 lanes, each running independent FP64 FMA chains for `iters` rounds;
+// *flops receives the launch's FP64 operation count.  launch_copy_peak:
+// dst[i] = src[i] for n doubles (16-byte aligned, not overlapping).
+hipError_t launch_fma_peak(double* sink, int blocks, int iters, hipStream_t s, double* flops);
+hipError_t launch_copy_peak(const double* src, double* dst, int64_t n, int blocks, hipStream_t s);
 // Zero the me x ne solution region (at xoff) of every listed block; me0, ne0
 // bound the block sizes.
 hipError_t launch_zero_blocks(const BlockDesc* blocks, int nblocks, int me0, int ne0, double* X,

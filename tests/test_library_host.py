@@ -83,6 +83,14 @@ def test_null_arguments_are_rejected(lib):
     assert lib.cyl_plan_set_physical(None, 1) == 1
     assert lib.cyl_trace_lift(None, None, None, None) == 1
     assert lib.cyl_disk_poisson_solve(None, 0, None, None) == 1
+    d = ctypes.c_double()
+    assert lib.cyl_device_peaks(None, None, None, 16, 0, None, None) == 1        # reps < 1
+    assert lib.cyl_device_peaks(None, None, None, 16, 1001, None, None) == 1     # reps > 1000
+    assert lib.cyl_device_peaks(None, None, None, 16, 3, None, ctypes.byref(d)) == 1   # copy without buffers
+    buf = (ctypes.c_double * 64)()
+    base = ctypes.addressof(buf) // 16 * 16 + 16
+    assert lib.cyl_device_peaks(None, base, base + 8, 4, 3, None, ctypes.byref(d)) == 1  # misaligned dst
+    assert lib.cyl_device_peaks(None, base, base + 16, 4, 3, None, ctypes.byref(d)) == 1  # overlap
 
 
 def test_adi_parameter_validation():
