@@ -87,6 +87,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-physical", action="store_true")
     ap.add_argument("--no-disk", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the 32^3 latency leg")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--cpu-modes", type=int, default=16,
@@ -393,6 +394,41 @@ def main():
                                    "transforms_ms": (dp["ms_transform_fwd"] + dp["ms_transform_inv"]) / args.steps,
                                    "config": {"workload": "disk_poisson_%d^3_value_space" % m,
                                               "forcing": "seeded decaying random CCF spectrum"}}
+
+    if not args.no_small:
+        # the smallest configuration (32^3, ADI tolerance 1e-12): bound by the
+        # latency of the ADI's sequential iterations; eager solves and the
+        # same solve captured once into a HIP graph and replayed
+        ms_ = ns_ = ps_ = 32
+        s32 = torch.cuda.Stream()
+        with torch.cuda.stream(s32):
+            plan32 = cyl.Plan(ms_, ns_, ps_, stream=s32)
+            f32 = plan32.transform_inv(torch.from_numpy(synth.smooth_coeffs(ms_, ns_, ps_, synth.SEED_BASE)).cuda())
+            u32 = torch.empty_like(f32)
+            _, info32 = plan32.poisson_solve(f32, adi_tol=1e-12, out=u32, info=True)
+            s32.synchronize()
+            reps = 200
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                plan32.poisson_solve(f32, adi_tol=1e-12, out=u32)
+            s32.synchronize()
+            eager_us = 1e6 * (time.perf_counter() - t0) / reps
+        g32 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g32, stream=s32):
+            plan32.poisson_solve(f32, adi_tol=1e-12, out=u32)
+        g32.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g32.replay()
+        torch.cuda.synchronize()
+        graph_us = 1e6 * (time.perf_counter() - t0) / reps
+        out["poisson_32"] = {"us_per_solve": eager_us, "solves_per_s": 1e6 / eager_us,
+                             "unknowns_per_s": ms_ * ns_ * ps_ * 1e6 / eager_us,
+                             "graph_us_per_solve": graph_us, "adi_iterations_max": info32["J_max"],
+                             "resid_ratio": info32["resid_ratio"],
+                             "config": {"workload": "poisson_32^3_value_space", "adi_tol": 1e-12}}
+        del plan32, g32
 
     if not args.no_heat:
         hp = cyl.Plan(128, 128, 128)

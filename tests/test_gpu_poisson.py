@@ -164,6 +164,39 @@ def test_fused_residual_matches_separate_launch(m, n, p):
     assert_close(fused, pb.poisson(f), TOL, "fused residual")
 
 
+@pytest.mark.parametrize("m,n,p,env", [(33, 30, 8, {}), (130, 120, 4, {}),
+                                       (130, 120, 4, {"CYLSPEC_PASSES": "2", "CYLSPEC_ADI_FUSED_RES": "2"})])
+def test_graph_captured_solve_replays_match_eager(m, n, p, env, monkeypatch):
+    """A solve captured into a HIP graph (the plan on the capturing stream,
+    its tables built by an eager solve first) replays bit-identically, every
+    replay, with eager solves in between."""
+    need_gpu()
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    banner("graph replay m=%d n=%d p=%d %s" % (m, n, p, env))
+    s = torch.cuda.Stream()
+    f = dev(smooth_values(m, n, p, S + 51 + m))
+    with torch.cuda.stream(s):
+        plan = cyl.Plan(m, n, p, stream=s)
+        u = torch.empty_like(f)
+        plan.poisson_solve(f, out=u)
+        s.synchronize()
+        ref = u.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.poisson_solve(f, out=u)
+    torch.cuda.synchronize()
+    for _ in range(4):
+        u.fill_(-1.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(u, ref)
+        with torch.cuda.stream(s):
+            plan.poisson_solve(f, out=u)
+        torch.cuda.synchronize()
+    assert_close(host(ref), pb.poisson(host(f)), TOL, "graph")
+
+
 def test_non_finite_input_reports_not_converged():
     need_gpu()
     m, n, p = 10, 10, 4
