@@ -261,8 +261,8 @@ def batched_heat(cyl, torch, synth, count, steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the path shards by Fourier mode; "
-              "see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the solver runs on a single device (sharding the "
+              "Fourier modes across GPUs is not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
