@@ -523,11 +523,19 @@ __global__ __launch_bounds__(512) void k_theta_fwd(const double* __restrict__ va
     const bool has1 = valid && (j0 + 1 < m);
     double2* buf = lds + d.Nb + li * line_stride(d.Nb);
     stage_twiddles(tws, d);
-    for (int l = t; l < p; l += TPL) {
+    // every load of the thread is issued before the first is used (p <= Nb
+    // <= kPts TPL), so the HBM latency is paid once per line, not per point
+    double2 v[kPts];
+#pragma unroll
+    for (int c = 0; c < kPts; ++c) {
+        const int l = t + c * TPL;
         const int64_t off = (static_cast<int64_t>(l) * n + k) * m + j0;
-        const double a = valid ? val[off] : 0.0;
-        const double b = has1 ? val[off + 1] : 0.0;
-        buf[P(l)] = load_chirped(make_double2(a, b), d, l);
+        v[c] = make_double2(valid && l < p ? val[off] : 0.0, has1 && l < p ? val[off + 1] : 0.0);
+    }
+#pragma unroll
+    for (int c = 0; c < kPts; ++c) {
+        const int l = t + c * TPL;
+        if (l < p) buf[P(l)] = load_chirped(v[c], d, l);
     }
     for (int l = p + t; l < d.Nb; l += TPL) buf[P(l)] = make_double2(0.0, 0.0);
     __syncthreads();
@@ -565,12 +573,23 @@ __global__ __launch_bounds__(512) void k_theta_inv(const double2* __restrict__ p
     const bool has1 = valid && (j0 + 1 < m);
     double2* buf = lds + d.Nb + li * line_stride(d.Nb);
     stage_twiddles(tws, d);
-    for (int l = t; l < p; l += TPL) {
+    // all loads first (as in k_theta_fwd)
+    double2 va[kPts], vb[kPts];
+#pragma unroll
+    for (int c = 0; c < kPts; ++c) {
+        const int l = t + c * TPL;
+        const int wq = (2 * l <= p) ? l : p - l;
+        const int64_t off = (static_cast<int64_t>(wq) * n + k) * m + j0;
+        va[c] = valid && l < p ? planes[off] : make_double2(0.0, 0.0);
+        vb[c] = has1 && l < p ? planes[off + 1] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int c = 0; c < kPts; ++c) {
+        const int l = t + c * TPL;
+        if (l >= p) break;
         const int wq = (2 * l <= p) ? l : p - l;
         const bool cj = 2 * l > p;
-        const int64_t off = (static_cast<int64_t>(wq) * n + k) * m + j0;
-        double2 ca = valid ? planes[off] : make_double2(0.0, 0.0);
-        double2 cb = has1 ? planes[off + 1] : make_double2(0.0, 0.0);
+        double2 ca = va[c], cb = vb[c];
         if (wq == 0 || 2 * wq == p) { ca.y = 0.0; cb.y = 0.0; }
         const double sg = (wq & 1) ? -1.0 : 1.0;
         if (cj) { ca.y = -ca.y; cb.y = -cb.y; }
