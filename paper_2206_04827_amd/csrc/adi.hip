@@ -1080,15 +1080,25 @@ __global__ __launch_bounds__(256) void k_rhs(const double2* __restrict__ F,
     const int mi = m - 2, ni = n - 2, tid = threadIdx.x;
     const double2* Fw = F + static_cast<int64_t>(w) * n * m;
     const double2* Lw = kLift ? L + static_cast<int64_t>(w) * n * m : nullptr;
-    for (int idx = tid; idx < kRL * kRA; idx += blockDim.x) {
+    // 256 threads: every load of the tile is issued before the first is used
+    constexpr int kIt = (kRL * kRA + 255) / 256;
+    double2 fv[kIt], lvv[kLift ? kIt : 1];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int idx = tid + 256 * it;
         const int ll = idx / kRA, al = idx - ll * kRA;
         const int a = i0 - 2 + al, l = k0 + ll;
-        double2 f = make_double2(0.0, 0.0), lv = make_double2(0.0, 0.0);
-        if (a >= 0 && a < m && l < n) {
-            f = Fw[static_cast<int64_t>(l) * m + a];
-            if (kLift) lv = Lw[static_cast<int64_t>(l) * m + a];
-        }
+        const bool in = idx < kRL * kRA && a >= 0 && a < m && l < n;
+        fv[it] = in ? Fw[static_cast<int64_t>(l) * m + a] : make_double2(0.0, 0.0);
+        if (kLift) lvv[it] = in ? Lw[static_cast<int64_t>(l) * m + a] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int idx = tid + 256 * it;
+        if (idx >= kRL * kRA) break;
+        double2 f = fv[it];
         if (kLift) {
+            const double2 lv = lvv[kLift ? it : 0];
             lt[idx] = lv;
             f = make_double2(f.x + cL * lv.x, f.y + cL * lv.y);
         }
@@ -1192,17 +1202,28 @@ __global__ __launch_bounds__(256) void k_recombine(const double* __restrict__ X,
         neb[b] = blocks[4 * p0 + b].ne;
         x1[b] = p1 >= 0 ? blocks[4 * p1 + b].xoff : 0;
     }
-    for (int idx = tid; idx < (kCA + 2) * (kCL + 2); idx += blockDim.x) {
+    // 256 threads: every load of the tile is issued before the first is used
+    constexpr int kIt = ((kCA + 2) * (kCL + 2) + 255) / 256;
+    double2 v[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int idx = tid + 256 * it;
         const int il = idx / (kCL + 2), kl = idx - il * (kCL + 2);
         const int i = a0 - 2 + il, k = l0 - 2 + kl;
-        double2 v = make_double2(0.0, 0.0);
-        if (i >= 0 && i < mi && k >= 0 && k < ni) {
+        v[it] = make_double2(0.0, 0.0);
+        if (idx < (kCA + 2) * (kCL + 2) && i >= 0 && i < mi && k >= 0 && k < ni) {
             const int b = 2 * (i & 1) + (k & 1);
             const int64_t o = static_cast<int64_t>(i >> 1) * neb[b] + (k >> 1);
-            v.x = X[x0[b] + o];
-            if (p1 >= 0) v.y = X[x1[b] + o];
+            v[it].x = X[x0[b] + o];
+            if (p1 >= 0) v[it].y = X[x1[b] + o];
         }
-        xs[kl * kCS + il] = v;
+    }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int idx = tid + 256 * it;
+        if (idx >= (kCA + 2) * (kCL + 2)) break;
+        const int il = idx / (kCL + 2), kl = idx - il * (kCL + 2);
+        xs[kl * kCS + il] = v[it];
     }
     __syncthreads();
     for (int idx = tid; idx < kCA * kCL; idx += blockDim.x) {
@@ -1243,10 +1264,23 @@ __device__ __forceinline__ void apply_tile(double* xs, double* zs, const BlockDe
     const int me = bd.me, ne = bd.ne;
     const int tid = threadIdx.x;
     const double* Xb = X + bd.xoff;
-    for (int idx = tid; idx < kTR * kTC; idx += blockDim.x) {
+    // 256 threads: every load of the tile is issued before the first is used
+    constexpr int kIt = (kTR * kTC + 255) / 256;
+    double xv[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int idx = tid + 256 * it;
         const int r = idx / kTC, c = idx - r * kTC;
         const int a = i0 - 2 + r, l = k0 - 1 + c;
-        xs[r * kTS + c] = (a >= 0 && a < me && l >= 0 && l < ne) ? Xb[static_cast<int64_t>(a) * ne + l] : 0.0;
+        xv[it] = (idx < kTR * kTC && a >= 0 && a < me && l >= 0 && l < ne) ? Xb[static_cast<int64_t>(a) * ne + l]
+                                                                          : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int idx = tid + 256 * it;
+        if (idx >= kTR * kTC) break;
+        const int r = idx / kTC, c = idx - r * kTC;
+        xs[r * kTS + c] = xv[it];
     }
     const double* zcol = ztabA + (bd.pz ? ne0 * 8 : 0);
     for (int idx = tid; idx < kTile * 8; idx += blockDim.x) {
