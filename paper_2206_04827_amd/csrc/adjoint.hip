@@ -106,17 +106,39 @@ __global__ __launch_bounds__(256) void k_apply_dot(const BlockDesc* __restrict__
     const int64_t slot = (static_cast<int64_t>(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     if (i0 >= me || k0 >= ne) return;
     const double* Xb = X + bd.xoff;
-    for (int idx = threadIdx.x; idx < kTR * kTC; idx += blockDim.x) {
+    const double* Yb = Yf + bd.xoff;
+    // 256 threads: the tile of X and this thread's values of Yf are all
+    // requested before the first is used
+    constexpr int kIt = (kTR * kTC + 255) / 256, kOut = kTile * kTile / 256;
+    double xv[kIt], yv[kOut];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int idx = threadIdx.x + 256 * it;
         const int r = idx / kTC, c = idx - r * kTC;
         const int a = i0 - 2 + r, l = k0 - 1 + c;
-        xs[r][c] = (a >= 0 && a < me && l >= 0 && l < ne) ? Xb[static_cast<int64_t>(a) * ne + l] : 0.0;
+        xv[it] = (idx < kTR * kTC && a >= 0 && a < me && l >= 0 && l < ne) ? Xb[static_cast<int64_t>(a) * ne + l]
+                                                                          : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < kOut; ++it) {
+        const int idx = threadIdx.x + 256 * it;
+        const int i = i0 + idx % kTile, k = k0 + idx / kTile;
+        yv[it] = (i < me && k < ne) ? Yb[static_cast<int64_t>(me - 1 - i) * ne + (ne - 1 - k)] : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int idx = threadIdx.x + 256 * it;
+        if (idx >= kTR * kTC) break;
+        const int r = idx / kTC, c = idx - r * kTC;
+        xs[r][c] = xv[it];
     }
     __syncthreads();
     const double* arow = atab + bd.w * a_wstride + (bd.pr ? me0 * 12 : 0);
     const double* zcol = ztabA + (bd.pz ? ne0 * 8 : 0);
-    const double* Yb = Yf + bd.xoff;
     double local = 0.0;
-    for (int idx = threadIdx.x; idx < kTile * kTile; idx += blockDim.x) {
+#pragma unroll
+    for (int it = 0; it < kOut; ++it) {
+        const int idx = threadIdx.x + 256 * it;
         const int di = idx % kTile, dk = idx / kTile;
         const int i = i0 + di, k = k0 + dk;
         if (i >= me || k >= ne) continue;
@@ -135,7 +157,7 @@ __global__ __launch_bounds__(256) void k_apply_dot(const BlockDesc* __restrict__
             sab += ar[da] * xb;
             scd += ar[6 + da] * xd;
         }
-        local += Yb[static_cast<int64_t>(me - 1 - i) * ne + (ne - 1 - k)] * (sab + scd);
+        local += yv[it] * (sab + scd);
     }
     red[threadIdx.x] = local;
     __syncthreads();
