@@ -62,12 +62,12 @@ STREAM_BYTES_PER_UNKNOWN_ITER = 40.0
 STREAM_PASS_BYTES = 8 * 16.0
 # HBM bytes per ADI launch at 256^3 (mean of the two passes, the first also
 # forming the residual) from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by
-# an elementwise kernel reading and writing 512 MiB: fetch x2.0, write x1.0),
+# copy kernels reading and writing 512 MiB: fetch x2.0, write x1.0),
 # valid for the ADI source whose SHA-256 starts with ADI_TRAFFIC_SHA, at ADI
 # tolerance ADI_TRAFFIC_TOL (the traffic scales with the iteration count);
 # reported as null otherwise.
-ADI_TRAFFIC_BYTES_256 = 2.354e9
-ADI_TRAFFIC_SHA = "65c9f20be455780d"
+ADI_TRAFFIC_BYTES_256 = 2.355e9
+ADI_TRAFFIC_SHA = "558949facb48cb8a"
 ADI_TRAFFIC_TOL = 1e-10
 
 
