@@ -126,6 +126,23 @@ def cpu_baseline(m, n, p, seed, nmodes, u_gpu=None):
     tr.inverse(U)
     t_inv = time.perf_counter() - t0
     t_total = t_fwd + t_inv + t_modes * p / len(ls)
+    # the same oracle with its BLAS/LAPACK limited to one thread (its FFTs are
+    # single-threaded either way), on the first two sampled wavenumbers
+    single = None
+    try:
+        from threadpoolctl import threadpool_limits
+        ls1 = ls[:2]
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            pb.poisson_coeffs(c, modes=ls1)
+            t_m1 = time.perf_counter() - t0
+        t1 = t_fwd + t_inv + t_m1 * p / len(ls1)
+        single = {"value": m * n * p / t1, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+                  "sample": ("the transforms timed above plus the per-mode solves of %d wavenumbers "
+                             "with BLAS/LAPACK on one thread, scaled to all %d; %.2f s measured, "
+                             "%.1f s extrapolated") % (len(ls1), p, t_m1, t1)}
+    except ImportError:
+        pass
     acc = None
     if u_gpu is not None:
         got = tr.forward(u_gpu)
@@ -141,7 +158,8 @@ def cpu_baseline(m, n, p, seed, nmodes, u_gpu=None):
                        "per-mode Bartels-Stewart + 2 extended-precision refinements timed on "
                        "%d of %d wavenumbers (every %d-th) and scaled to all; %.2f s measured, "
                        "%.1f s extrapolated") % (m, len(ls), p, max(1, p // nmodes),
-                                                 t_fwd + t_inv + t_modes, t_total)}
+                                                 t_fwd + t_inv + t_modes, t_total),
+            "single_thread": single}
 
 
 def heat_fwd_adjoint(cyl, torch, synth, reps, size=192, steps=200, every=20):
