@@ -67,3 +67,19 @@ def test_random_size_disk(m, n, p):
     f = smooth_values(m, n, p, S + 331 + m)
     got = host(cyl.Plan(m, n, p).disk_poisson_solve(dev(f)))
     assert_close(got, pb.disk_poisson(f), TOL, "disk")
+
+
+@pytest.mark.parametrize("m,n,p,seed", [(10, 8, 12, 1), (17, 13, 11, 2), (33, 21, 16, 3), (64, 40, 12, 4)])
+def test_random_polynomial_solution_exact(m, n, p, seed):
+    """Random cubic q(x, y, z), u = (1 - x^2 - y^2)(1 - z^2) q, Laplacian by
+    exact monomial differentiation: the GPU solve returns u to rounding,
+    independently of the oracle."""
+    from tests.test_oracle_random_polynomials import N_COEFFS, _manufactured
+    need_gpu()
+    banner("random polynomial m=%d n=%d p=%d" % (m, n, p))
+    coeffs = np.random.default_rng(S + 340 + seed).uniform(-1.0, 1.0, N_COEFFS)
+    u, f = _manufactured(m, n, p, coeffs)
+    got = host(cyl.Plan(m, n, p).poisson_solve(dev(f)))
+    err = np.max(np.abs(got - u)) / max(1.0, np.max(np.abs(u)))
+    print("  rel max %.3e" % err)
+    assert err <= 1e-11
