@@ -6,13 +6,17 @@ The sizes are drawn around the thresholds where the library changes kernels
 above; tile edges of the transforms and of the right-side, recombination and
 residual kernels), with odd and even counts and a single theta point."""
 
+import itertools
+
 import numpy as np
 import pytest
 
 import paper_2206_04827_amd as cyl
 import synth
 from oracle import problems as pb
+from oracle import transforms as tr
 from tests.gpu_common import S, TOL, assert_close, banner, dev, host, need_gpu, smooth_values
+from tests.test_oracle_random_polynomials import N_COEFFS, _manufactured, _poly_add, _poly_d2, _poly_eval
 
 pytestmark = pytest.mark.gpu
 
@@ -74,7 +78,6 @@ def test_random_polynomial_solution_exact(m, n, p, seed):
     """Random cubic q(x, y, z), u = (1 - x^2 - y^2)(1 - z^2) q, Laplacian by
     exact monomial differentiation: the GPU solve returns u to rounding,
     independently of the oracle."""
-    from tests.test_oracle_random_polynomials import N_COEFFS, _manufactured
     need_gpu()
     banner("random polynomial m=%d n=%d p=%d" % (m, n, p))
     coeffs = np.random.default_rng(S + 340 + seed).uniform(-1.0, 1.0, N_COEFFS)
@@ -83,3 +86,34 @@ def test_random_polynomial_solution_exact(m, n, p, seed):
     err = np.max(np.abs(got - u)) / max(1.0, np.max(np.abs(u)))
     print("  rel max %.3e" % err)
     assert err <= 1e-11
+
+
+@pytest.mark.parametrize("m,n,p,seed", [(14, 12, 12, 5), (40, 33, 16, 6)])
+def test_random_polynomial_physical_and_traces(m, n, p, seed):
+    """The same random polynomials are single-valued smooth fields: the
+    physical-parity fast path returns them exactly; and q itself (nonzero on
+    the boundary) is recovered from its Laplacian and its boundary traces."""
+    need_gpu()
+    banner("random polynomial physical/traces m=%d n=%d p=%d" % (m, n, p))
+    coeffs = np.random.default_rng(S + 350 + seed).uniform(-1.0, 1.0, N_COEFFS)
+    u, f = _manufactured(m, n, p, coeffs)
+    plan = cyl.Plan(m, n, p)
+    plan.set_physical(True)
+    got = host(plan.poisson_solve(dev(f)))
+    assert np.max(np.abs(got - u)) <= 1e-11 * max(1.0, np.max(np.abs(u)))
+    plan.set_physical(False)
+    # v = u + b with b a random cubic that does not vanish on the boundary:
+    # lap v = f + lap b, and v's values on the faces are the Dirichlet data
+    b_coeffs = np.random.default_rng(S + 360 + seed).uniform(-1.0, 1.0, N_COEFFS)
+    exps = [e for e in itertools.product(range(4), repeat=3) if sum(e) <= 3]
+    bq = {e: c for e, c in zip(exps, b_coeffs)}
+    lap_b = _poly_add(_poly_d2(bq, 0), _poly_d2(bq, 1), _poly_d2(bq, 2))
+    r, z, th = tr.grid(m, n, p)
+    TH, Z, R = np.meshgrid(th, z, r, indexing="ij")
+    X, Y = R * np.cos(TH), R * np.sin(TH)
+    v = u + _poly_eval(bq, X, Y, Z)
+    fv = f + _poly_eval(lap_b, X, Y, Z)
+    rface = np.ascontiguousarray(np.stack([v[:, :, 0], v[:, :, -1]]))
+    zface = np.ascontiguousarray(np.stack([v[:, 0, :], v[:, -1, :]]))
+    got = host(plan.poisson_solve(dev(fv), bc_traces=(dev(rface), dev(zface))))
+    assert np.max(np.abs(got - v)) <= 1e-11 * max(1.0, np.max(np.abs(v)))
