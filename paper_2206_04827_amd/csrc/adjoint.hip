@@ -99,6 +99,7 @@ __global__ __launch_bounds__(256) void k_apply_dot(const BlockDesc* __restrict__
                                                    const double* __restrict__ ztabA, int ne0,
                                                    double* __restrict__ partials) {
     __shared__ double xs[kTR][kTC + 1];
+    __shared__ double zs[kTile * 8];
     __shared__ double red[256];
     const BlockDesc bd = blocks[blockIdx.z];
     const int me = bd.me, ne = bd.ne;
@@ -125,6 +126,17 @@ __global__ __launch_bounds__(256) void k_apply_dot(const BlockDesc* __restrict__
         const int i = i0 + idx % kTile, k = k0 + idx / kTile;
         yv[it] = (i < me && k < ne) ? Yb[static_cast<int64_t>(me - 1 - i) * ne + (ne - 1 - k)] : 0.0;
     }
+    // the tile's column records (32 columns of 8, one per thread) go to LDS;
+    // a thread's row is the same in every output it computes, so its row
+    // records are read once
+    const double* arow = atab + bd.w * a_wstride + (bd.pr ? me0 * 12 : 0);
+    const double* zcol = ztabA + (bd.pz ? ne0 * 8 : 0);
+    static_assert(kTile * 8 == 256 && kTile * kTile % 256 == 0, "one record per thread; whole rows per output");
+    const int di = threadIdx.x % kTile, i = i0 + di;
+    const double zv = (k0 + static_cast<int>(threadIdx.x >> 3) < ne) ? zcol[k0 * 8 + threadIdx.x] : 0.0;
+    double ar[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) ar[q] = i < me ? arow[i * 12 + q] : 0.0;
 #pragma unroll
     for (int it = 0; it < kIt; ++it) {
         const int idx = threadIdx.x + 256 * it;
@@ -132,18 +144,16 @@ __global__ __launch_bounds__(256) void k_apply_dot(const BlockDesc* __restrict__
         const int r = idx / kTC, c = idx - r * kTC;
         xs[r][c] = xv[it];
     }
+    zs[threadIdx.x] = zv;
     __syncthreads();
-    const double* arow = atab + bd.w * a_wstride + (bd.pr ? me0 * 12 : 0);
-    const double* zcol = ztabA + (bd.pz ? ne0 * 8 : 0);
     double local = 0.0;
 #pragma unroll
     for (int it = 0; it < kOut; ++it) {
         const int idx = threadIdx.x + 256 * it;
-        const int di = idx % kTile, dk = idx / kTile;
-        const int i = i0 + di, k = k0 + dk;
+        const int dk = idx / kTile;
+        const int k = k0 + dk;
         if (i >= me || k >= ne) continue;
-        const double* ar = arow + i * 12;
-        const double* zc = zcol + k * 8;
+        const double* zc = zs + dk * 8;
         double sab = 0.0, scd = 0.0;
 #pragma unroll
         for (int da = 0; da < 6; ++da) {
