@@ -161,3 +161,29 @@ def test_physical_heat_handles_are_rejected_by_batch_and_grad():
     with pytest.raises(cyl.CylError) as e:
         cyl.Batch([H])
     assert e.value.status == 2
+
+
+@pytest.mark.parametrize("m,n,p", [(10, 9, 6), (40, 36, 8)])
+def test_physical_heat_with_lift(m, n, p):
+    """Physical-parity stepping with Dirichlet data through a (physical)
+    lift: the steady state of a polynomial solution is kept exactly, and a
+    run from a physical initial state matches the oracle's lifted heat run."""
+    need_gpu()
+    banner("physical heat with lift m=%d n=%d p=%d" % (m, n, p))
+    r, z, th = tr.grid(m, n, p)
+    TH, Z, R = np.meshgrid(th, z, r, indexing="ij")
+    X, Y = R * np.cos(TH), R * np.sin(TH)
+    psi = 2.0 + X * Z + Y * Y * Z + Z ** 2
+    alpha = 0.7
+    g = -alpha * (2 * Z + 2.0)
+    lift = psi + (1 - R ** 2) * (1 - Z ** 2) * X
+    plan = cyl.Plan(m, n, p)
+    plan.set_physical(True)
+    H = cyl.Heat(plan, [dev(psi)], dev(g), alpha, 1e-2, 1, 1e-12, bc_lift=dev(lift))
+    H.step(5)
+    assert np.max(np.abs(host(H.read()) - psi)) < 1e-12
+    T0 = synth.physical_values(m, n, p, S + 170) * (1 - R ** 2) * (1 - Z ** 2) + lift
+    g2 = synth.physical_values(m, n, p, S + 171)
+    H2 = cyl.Heat(plan, [dev(T0)], dev(g2), 0.9, 2e-3, 1, 1e-12, bc_lift=dev(lift))
+    H2.step(4)
+    assert_close(host(H2.read()), pb.heat([T0], g2, 0.9, 2e-3, 4, order=1, lift=lift), TOL, "physical lifted heat")
