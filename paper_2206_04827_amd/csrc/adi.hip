@@ -683,7 +683,7 @@ __device__ __forceinline__ void half_barrier() {
     else lds_barrier();
 }
 
-template <int LD, bool kGS>
+template <int LD, bool kGS, int GB>
 __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const BlockDesc& bd,
                                                 const double* __restrict__ E, double* X,
                                                 const double* __restrict__ rtab,
@@ -697,6 +697,11 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
     // rows per software-pipelined group: 4 when the state is in global memory
     // (512-thread workgroups leave 256 registers per thread)
     constexpr int GG = kGS ? 4 : G;
+    // GB: rows/columns per group of the backward r sweeps and of the z
+    // sweeps (16 when every half of every block is a multiple of 16: more
+    // loads in flight per wait; the forward r sweeps, with twice the records
+    // per row, keep GG)
+    static_assert(!kGS || GB == GG, "groups of the global-state variant");
     double* S = kGS ? gS : sm;
     const int nr = (mp + kRCouple) * kRRec, nz = (np + kZCouple) * kZRec;
     double* RCs = kGS ? sm : S + mp * LD;
@@ -746,8 +751,8 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
             for (int r = 0; r < 5; ++r)
                 y[r] = K5[5 * r] * v[0] + K5[5 * r + 1] * v[1] + K5[5 * r + 2] * v[2] +
                        K5[5 * r + 3] * v[3] + K5[5 * r + 4] * v[4];
-            if (top) rs_top_bwd<LD, GG>(S, tr, line, RCs, y[2], y[3], y[4]);
-            else rs_bot_bwd<LD, GG>(S, mp, tr, line, RCs, y[1], y[0]);
+            if (top) rs_top_bwd<LD, GB>(S, tr, line, RCs, y[2], y[3], y[4]);
+            else rs_bot_bwd<LD, GB>(S, mp, tr, line, RCs, y[1], y[0]);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
@@ -757,10 +762,10 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
         double* row = S + line * LD;
         if (line < me) {
             if (top) {
-                XC[line] = zs_top_fwd<GG>(row, tz, ZCs);
+                XC[line] = zs_top_fwd<GB>(row, tz, ZCs);
             } else {
                 double a, b;
-                zs_bot_fwd<GG>(row, np, tz, ZCs, &a, &b);
+                zs_bot_fwd<GB>(row, np, tz, ZCs, &a, &b);
                 XC[L + line] = a;
                 XC[2 * L + line] = b;
             }
@@ -773,11 +778,11 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
             const double y1 = K3[3] * v0 + K3[4] * v1 + K3[5] * v2;
             const double y2 = K3[6] * v0 + K3[7] * v1 + K3[8] * v2;
             if (top) {
-                if (more) zs_top_bwd<false, GG>(row, tz, ZCs, y1, y2);
-                else zs_top_bwd<true, GG>(row, tz, ZCs, y1, y2);
+                if (more) zs_top_bwd<false, GB>(row, tz, ZCs, y1, y2);
+                else zs_top_bwd<true, GB>(row, tz, ZCs, y1, y2);
             } else {
-                if (more) zs_bot_bwd<false, GG>(row, np, tz, ZCs, y0);
-                else zs_bot_bwd<true, GG>(row, np, tz, ZCs, y0);
+                if (more) zs_bot_bwd<false, GB>(row, np, tz, ZCs, y0);
+                else zs_bot_bwd<true, GB>(row, np, tz, ZCs, y0);
             }
         }
         __builtin_amdgcn_s_waitcnt(0);
@@ -906,7 +911,7 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
     }
 }
 
-template <int NP>
+template <int NP, int GB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_adi_split(const BlockDesc* __restrict__ blocks, const double* __restrict__ E, double* X,
                  const double* __restrict__ rtab, const double* __restrict__ ztab,
@@ -918,7 +923,7 @@ void k_adi_split(const BlockDesc* __restrict__ blocks, const double* __restrict_
         const AdiPtrs q = pp[bd.prob];
         E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
     }
-    adi_block_split<NP + 1, false>(sm, nullptr, bd, E, X, rtab, ztab, vmu, accumulate, res);
+    adi_block_split<NP + 1, false, GB>(sm, nullptr, bd, E, X, rtab, ztab, vmu, accumulate, res);
 }
 
 // Blocks too large for LDS (n up to 514): split sweeps with the state in
@@ -937,7 +942,7 @@ __global__ __launch_bounds__(512) void k_adi_split_gs(const BlockDesc* __restric
         const AdiPtrs q = pp[bd.prob];
         E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
     }
-    adi_block_split<NP + 1, true>(sm, state + static_cast<int64_t>(blockIdx.x) * state_stride, bd, E, X, rtab,
+    adi_block_split<NP + 1, true, 4>(sm, state + static_cast<int64_t>(blockIdx.x) * state_stride, bd, E, X, rtab,
                                   ztab, vmu, accumulate, res);
 }
 
@@ -1425,8 +1430,12 @@ template <int NP>
 hipError_t launch_split(const BlockDesc* blocks, int nblocks, int threads, const double* E,
                         double* X, const double* rtab, const double* ztab, const double* vmu,
                         bool accumulate, size_t lds_bytes, hipStream_t s, const AdiPtrs* pp,
-                        const ResArgs& res) {
-    hipLaunchKernelGGL(k_adi_split<NP>, dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
+                        const ResArgs& res, bool g16) {
+    if (g16)
+        hipLaunchKernelGGL((k_adi_split<NP, 16>), dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
+                           rtab, ztab, vmu, accumulate ? 1 : 0, pp, res);
+    else
+        hipLaunchKernelGGL((k_adi_split<NP, G>), dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
                            rtab, ztab, vmu, accumulate ? 1 : 0, pp, res);
     return hipGetLastError();
 }
@@ -1443,7 +1452,10 @@ hipError_t launch_split_gs(const BlockDesc* blocks, int nblocks, int threads, co
 
 template <int NP>
 hipError_t set_split_limit(size_t bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_split<NP>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_split<NP, G>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_split<NP, 16>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
 
@@ -1475,6 +1487,10 @@ hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, int np0
     return hipGetLastError();
 }
 
+bool adi_split_g16(const BlockDesc& b) {
+    return b.tr % 16 == 0 && (b.mp - b.tr) % 16 == 0 && b.tz % 16 == 0 && (b.np - b.tz) % 16 == 0;
+}
+
 size_t adi_split_lds_bytes(int mp0, int np0) {
     auto chunks = [](int x) { return static_cast<size_t>((x + 127) / 128 * 128); };
     const size_t doubles = static_cast<size_t>(mp0) * (np0 + 1) + chunks((mp0 + kRCouple) * kRRec) +
@@ -1485,11 +1501,11 @@ size_t adi_split_lds_bytes(int mp0, int np0) {
 hipError_t launch_adi_split(const BlockDesc* blocks, int nblocks, int threads, int np0,
                             const double* E, double* X, const double* rtab, const double* ztab,
                             const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
-                            const AdiPtrs* pp, const ResArgs* res) {
+                            const AdiPtrs* pp, const ResArgs* res, bool g16) {
     if (threads < 128 || threads > 256 || threads % 128 != 0) return hipErrorInvalidValue;
     const ResArgs ra = res ? *res : ResArgs{nullptr, nullptr, nullptr, 0, 0, 0};
     switch (np0) {
-#define CYL_CASE(v) case v: return launch_split<v>(blocks, nblocks, threads, E, X, rtab, ztab, vmu, accumulate, lds_bytes, s, pp, ra);
+#define CYL_CASE(v) case v: return launch_split<v>(blocks, nblocks, threads, E, X, rtab, ztab, vmu, accumulate, lds_bytes, s, pp, ra, g16);
         CYL_NP_CASES(CYL_CASE)
 #undef CYL_CASE
         default: return hipErrorInvalidValue;

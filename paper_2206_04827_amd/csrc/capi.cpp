@@ -120,6 +120,7 @@ struct Setup {
     // physical parity: the blocks with r-parity = w (mod 2), and the others
     DevMem blocks_phys, blocks_skip;
     int n_phys = 0, n_skip = 0;
+    bool g16 = false;                // every block's halves are multiples of 16
 };
 
 enum Phase { PH_FWD, PH_RHS, PH_ADI, PH_RES, PH_REC, PH_INV, PH_HRHS, PH_PROJ, PH_ADJ, PH_COUNT };
@@ -195,6 +196,7 @@ struct BatchLaunch {
     size_t lds = 0;
     int nblocks = 0;
     int64_t state_stride = 0;
+    bool g16 = false;             // split sweeps: every block's halves are multiples of 16
     std::unique_ptr<cyl::DevMem> blocks, state;
 };
 
@@ -374,6 +376,8 @@ std::unique_ptr<Setup> make_setup(cyl_plan_t pl, double ka, double eps, bool fli
     upload(s->ztab, s->h.ztab);
     upload(s->vmu, s->h.vmu);
     upload(s->blocks, s->hblocks);
+    s->g16 = !s->hblocks.empty() &&
+             std::all_of(s->hblocks.begin(), s->hblocks.end(), [](const BlockDesc& b) { return adi_split_g16(b); });
     {
         std::vector<BlockDesc> keep, skip;
         for (const BlockDesc& b : s->hblocks) (b.pr == (std::abs(b.w) & 1) ? keep : skip).push_back(b);
@@ -514,7 +518,7 @@ void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X, bool physica
         else if (pl->adi_split)
             hip_check(launch_adi_split(blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
                                        s->rtab.as<double>(), s->ztab.as<double>(), s->vmu.as<double>(),
-                                       pass > 0, pl->lds_bytes, pl->stream, nullptr, rp),
+                                       pass > 0, pl->lds_bytes, pl->stream, nullptr, rp, s->g16),
                       "adi");
         else
             hip_check(launch_adi(blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
@@ -791,6 +795,7 @@ std::vector<BatchLaunch> build_launches(const std::vector<BlockRef>& refs, int g
         std::vector<BlockDesc> hb;
         hb.reserve(v.size());
         for (const BlockRef* r : v) hb.push_back(r->b);
+        l.g16 = l.kind == 0 && std::all_of(hb.begin(), hb.end(), [](const BlockDesc& b) { return adi_split_g16(b); });
         l.blocks = std::make_unique<DevMem>();
         upload(*l.blocks, hb);
         out.push_back(std::move(l));
@@ -803,7 +808,7 @@ void run_adi_launches(hipStream_t st, const std::vector<BatchLaunch>& ls, const 
         const BlockDesc* bl = l.blocks->as<BlockDesc>();
         if (l.kind == 0)
             hip_check(launch_adi_split(bl, l.nblocks, l.threads, l.np, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                       acc, l.lds, st, pp), "batched adi");
+                                       acc, l.lds, st, pp, nullptr, l.g16), "batched adi");
         else if (l.kind == 3)
             hip_check(launch_adi_split_gs(bl, l.nblocks, l.threads, l.np, nullptr, nullptr, l.state->as<double>(),
                                           l.state_stride, nullptr, nullptr, nullptr, acc, l.lds, st, pp),

@@ -132,7 +132,11 @@ hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, int np0
 hipError_t launch_adi_split(const BlockDesc* blocks, int nblocks, int threads, int np0,
                             const double* E, double* X, const double* rtab, const double* ztab,
                             const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
-                            const AdiPtrs* pp = nullptr, const ResArgs* res = nullptr);
+                            const AdiPtrs* pp = nullptr, const ResArgs* res = nullptr, bool g16 = false);
+// Every half of the block is a multiple of 16 rows / columns (the split kernel's
+// backward r sweeps and z sweeps may then take groups of 16; g16 of a launch
+// needs it for all its blocks).
+bool adi_split_g16(const BlockDesc& b);
 // LDS bytes of the split kernel for padded block sizes mp0 x np0.
 size_t adi_split_lds_bytes(int mp0, int np0);
 // Split sweeps with the block state in global memory (np0 in 136..256, a
