@@ -376,8 +376,11 @@ std::unique_ptr<Setup> make_setup(cyl_plan_t pl, double ka, double eps, bool fli
     upload(s->ztab, s->h.ztab);
     upload(s->vmu, s->h.vmu);
     upload(s->blocks, s->hblocks);
-    s->g16 = !s->hblocks.empty() &&
+    s->g16 = env_int("CYLSPEC_ADI_G16", 1) != 0 && !s->hblocks.empty() &&
              std::all_of(s->hblocks.begin(), s->hblocks.end(), [](const BlockDesc& b) { return adi_split_g16(b); });
+    if (env_int("CYLSPEC_LOG", 0) > 0 && pl->adi_split && !pl->split_gs)
+        std::fprintf(stderr, "[cylspec] ADI tables: %zu blocks, %d rows per group in the backward r and the z sweeps\n",
+                     s->hblocks.size(), s->g16 ? 16 : 8);
     {
         std::vector<BlockDesc> keep, skip;
         for (const BlockDesc& b : s->hblocks) (b.pr == (std::abs(b.w) & 1) ? keep : skip).push_back(b);
@@ -795,7 +798,7 @@ std::vector<BatchLaunch> build_launches(const std::vector<BlockRef>& refs, int g
         std::vector<BlockDesc> hb;
         hb.reserve(v.size());
         for (const BlockRef* r : v) hb.push_back(r->b);
-        l.g16 = l.kind == 0 && std::all_of(hb.begin(), hb.end(), [](const BlockDesc& b) { return adi_split_g16(b); });
+        l.g16 = l.kind == 0 && env_int("CYLSPEC_ADI_G16", 1) != 0 && std::all_of(hb.begin(), hb.end(), [](const BlockDesc& b) { return adi_split_g16(b); });
         l.blocks = std::make_unique<DevMem>();
         upload(*l.blocks, hb);
         out.push_back(std::move(l));

@@ -164,6 +164,28 @@ def test_fused_residual_matches_separate_launch(m, n, p):
     assert_close(fused, pb.poisson(f), TOL, "fused residual")
 
 
+@pytest.mark.parametrize("m,n,p", [(256, 256, 4), (192, 192, 6)])
+def test_adi_16_row_groups_match_8(m, n, p, capfd):
+    """The LDS split kernel's two instances, 16 rows per group in the backward
+    r and the z sweeps (picked where every block's halves are multiples of 16,
+    as on these grids) and 8 rows everywhere, give bit-identical solutions
+    (grouping changes when loads are issued, not the arithmetic of a row), and
+    they match the oracle."""
+    need_gpu()
+    banner("adi row groups m=%d n=%d p=%d" % (m, n, p))
+    f = smooth_values(m, n, p, S + 43 + m)
+    g16 = _with_env({"CYLSPEC_LOG": "1"}, lambda: _solve_values(m, n, p, f))
+    log16 = capfd.readouterr().err
+    g8 = _with_env({"CYLSPEC_LOG": "1", "CYLSPEC_ADI_G16": "0"}, lambda: _solve_values(m, n, p, f))
+    log8 = capfd.readouterr().err
+    assert "16 rows per group" in log16, log16
+    assert "8 rows per group" in log8, log8
+    rel = np.max(np.abs(g16 - g8)) / np.max(np.abs(g8))
+    print("  16-row vs 8-row groups rel max %.3e" % rel)
+    assert rel == 0.0
+    assert_close(g16, pb.poisson(f), TOL, "16-row groups")
+
+
 @pytest.mark.parametrize("m,n,p,env", [(33, 30, 8, {}), (130, 120, 4, {}),
                                        (130, 120, 4, {"CYLSPEC_PASSES": "2", "CYLSPEC_ADI_FUSED_RES": "2"})])
 def test_graph_captured_solve_replays_match_eager(m, n, p, env, monkeypatch):
