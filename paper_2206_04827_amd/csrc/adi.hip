@@ -694,14 +694,15 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
     const int tid = threadIdx.x, nt = blockDim.x, L = nt >> 1;
     const int line = tid % L;
     const bool top = tid < L;
-    // rows per software-pipelined group: 4 when the state is in global memory
-    // (512-thread workgroups leave 256 registers per thread)
+    // rows per software-pipelined group of the forward r sweeps: 4 when the
+    // state is in global memory (512-thread workgroups leave 256 registers
+    // per thread)
     constexpr int GG = kGS ? 4 : G;
     // GB: rows/columns per group of the backward r sweeps and of the z
-    // sweeps (16 when every half of every block is a multiple of 16: more
-    // loads in flight per wait; the forward r sweeps, with twice the records
-    // per row, keep GG)
-    static_assert(!kGS || GB == GG, "groups of the global-state variant");
+    // sweeps, whose rows carry fewer records: 8 with the state in global
+    // memory; 16 in LDS when every half of every block is a multiple of 16.
+    // More loads in flight per wait.
+    static_assert(GB % GG == 0, "groups of the backward and z sweeps");
     double* S = kGS ? gS : sm;
     const int nr = (mp + kRCouple) * kRRec, nz = (np + kZCouple) * kZRec;
     double* RCs = kGS ? sm : S + mp * LD;
@@ -942,7 +943,7 @@ __global__ __launch_bounds__(512) void k_adi_split_gs(const BlockDesc* __restric
         const AdiPtrs q = pp[bd.prob];
         E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
     }
-    adi_block_split<NP + 1, true, 4>(sm, state + static_cast<int64_t>(blockIdx.x) * state_stride, bd, E, X, rtab,
+    adi_block_split<NP + 1, true, 8>(sm, state + static_cast<int64_t>(blockIdx.x) * state_stride, bd, E, X, rtab,
                                   ztab, vmu, accumulate, res);
 }
 
