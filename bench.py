@@ -67,7 +67,7 @@ STREAM_PASS_BYTES = 8 * 16.0
 # tolerance ADI_TRAFFIC_TOL (the traffic scales with the iteration count);
 # reported as null otherwise.
 ADI_TRAFFIC_BYTES_256 = 2.354e9
-ADI_TRAFFIC_SHA = "9fb81eb6c977741f"
+ADI_TRAFFIC_SHA = "69e1882d24fd182a"
 ADI_TRAFFIC_TOL = 1e-10
 
 
