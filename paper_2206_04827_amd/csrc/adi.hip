@@ -683,7 +683,7 @@ __device__ __forceinline__ void half_barrier() {
     else lds_barrier();
 }
 
-template <int LD, bool kGS, int GB>
+template <int LD, bool kGS, int GB, int GZF = GB>
 __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const BlockDesc& bd,
                                                 const double* __restrict__ E, double* X,
                                                 const double* __restrict__ rtab,
@@ -701,8 +701,10 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
     // GB: rows/columns per group of the backward r sweeps and of the z
     // sweeps, whose rows carry fewer records: 8 with the state in global
     // memory; 16 in LDS when every half of every block is a multiple of 16.
-    // More loads in flight per wait.
-    static_assert(GB % GG == 0, "groups of the backward and z sweeps");
+    // More loads in flight per wait.  GZF: columns per group of the forward
+    // z sweeps (three values per column): 16 with the state in global memory
+    // when every z half is a multiple of 16.
+    static_assert(GB % GG == 0 && GZF % GB == 0, "groups of the backward and z sweeps");
     double* S = kGS ? gS : sm;
     const int nr = (mp + kRCouple) * kRRec, nz = (np + kZCouple) * kZRec;
     double* RCs = kGS ? sm : S + mp * LD;
@@ -763,10 +765,10 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
         double* row = S + line * LD;
         if (line < me) {
             if (top) {
-                XC[line] = zs_top_fwd<GB>(row, tz, ZCs);
+                XC[line] = zs_top_fwd<GZF>(row, tz, ZCs);
             } else {
                 double a, b;
-                zs_bot_fwd<GB>(row, np, tz, ZCs, &a, &b);
+                zs_bot_fwd<GZF>(row, np, tz, ZCs, &a, &b);
                 XC[L + line] = a;
                 XC[2 * L + line] = b;
             }
@@ -929,7 +931,7 @@ void k_adi_split(const BlockDesc* __restrict__ blocks, const double* __restrict_
 
 // Blocks too large for LDS (n up to 514): split sweeps with the state in
 // global memory, slot blockIdx.x of `state` (state_stride doubles each).
-template <int NP>
+template <int NP, int GZF>
 __global__ __launch_bounds__(512) void k_adi_split_gs(const BlockDesc* __restrict__ blocks,
                                                       const double* __restrict__ E, double* X,
                                                       double* state, int64_t state_stride,
@@ -943,7 +945,7 @@ __global__ __launch_bounds__(512) void k_adi_split_gs(const BlockDesc* __restric
         const AdiPtrs q = pp[bd.prob];
         E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
     }
-    adi_block_split<NP + 1, true, 8>(sm, state + static_cast<int64_t>(blockIdx.x) * state_stride, bd, E, X, rtab,
+    adi_block_split<NP + 1, true, 8, GZF>(sm, state + static_cast<int64_t>(blockIdx.x) * state_stride, bd, E, X, rtab,
                                   ztab, vmu, accumulate, res);
 }
 
@@ -1445,8 +1447,12 @@ template <int NP>
 hipError_t launch_split_gs(const BlockDesc* blocks, int nblocks, int threads, const double* E, double* X,
                            double* state, int64_t state_stride, const double* rtab, const double* ztab,
                            const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
-                           const AdiPtrs* pp, const ResArgs& res) {
-    hipLaunchKernelGGL(k_adi_split_gs<NP>, dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
+                           const AdiPtrs* pp, const ResArgs& res, bool z16) {
+    if (z16)
+        hipLaunchKernelGGL((k_adi_split_gs<NP, 16>), dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
+                           state, state_stride, rtab, ztab, vmu, accumulate ? 1 : 0, pp, res);
+    else
+        hipLaunchKernelGGL((k_adi_split_gs<NP, 8>), dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
                            state, state_stride, rtab, ztab, vmu, accumulate ? 1 : 0, pp, res);
     return hipGetLastError();
 }
@@ -1462,7 +1468,10 @@ hipError_t set_split_limit(size_t bytes) {
 
 template <int NP>
 hipError_t set_split_gs_limit(size_t bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_split_gs<NP>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_split_gs<NP, 8>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_split_gs<NP, 16>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
 
@@ -1487,6 +1496,8 @@ hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, int np0
                            state_stride, rtab, ztab, vmu, accumulate ? 1 : 0, pp);
     return hipGetLastError();
 }
+
+bool adi_split_gs_z16(const BlockDesc& b) { return b.tz % 16 == 0 && (b.np - b.tz) % 16 == 0; }
 
 bool adi_split_g16(const BlockDesc& b) {
     return b.tr % 16 == 0 && (b.mp - b.tr) % 16 == 0 && b.tz % 16 == 0 && (b.np - b.tz) % 16 == 0;
@@ -1534,11 +1545,11 @@ hipError_t launch_adi_split_gs(const BlockDesc* blocks, int nblocks, int threads
                                const double* E, double* X, double* state, int64_t state_stride,
                                const double* rtab, const double* ztab, const double* vmu,
                                bool accumulate, size_t lds_bytes, hipStream_t s, const AdiPtrs* pp,
-                               const ResArgs* res) {
+                               const ResArgs* res, bool z16) {
     if (threads < 128 || threads > 512 || threads % 128 != 0) return hipErrorInvalidValue;
     const ResArgs ra = res ? *res : ResArgs{nullptr, nullptr, nullptr, 0, 0, 0};
     switch (np0) {
-#define CYL_CASE(v) case v: return launch_split_gs<v>(blocks, nblocks, threads, E, X, state, state_stride, rtab, ztab, vmu, accumulate, lds_bytes, s, pp, ra);
+#define CYL_CASE(v) case v: return launch_split_gs<v>(blocks, nblocks, threads, E, X, state, state_stride, rtab, ztab, vmu, accumulate, lds_bytes, s, pp, ra, z16);
         CYL_NP_GS_CASES(CYL_CASE)
 #undef CYL_CASE
         default: return hipErrorInvalidValue;

@@ -121,6 +121,7 @@ struct Setup {
     DevMem blocks_phys, blocks_skip;
     int n_phys = 0, n_skip = 0;
     bool g16 = false;                // every block's halves are multiples of 16
+    bool z16 = false;                // every block's z halves are multiples of 16
 };
 
 enum Phase { PH_FWD, PH_RHS, PH_ADI, PH_RES, PH_REC, PH_INV, PH_HRHS, PH_PROJ, PH_ADJ, PH_COUNT };
@@ -196,7 +197,7 @@ struct BatchLaunch {
     size_t lds = 0;
     int nblocks = 0;
     int64_t state_stride = 0;
-    bool g16 = false;             // split sweeps: every block's halves are multiples of 16
+    bool g16 = false;             // 16-row groups: LDS split (kind 0) or forward z of the global-state split (kind 3)
     std::unique_ptr<cyl::DevMem> blocks, state;
 };
 
@@ -378,9 +379,14 @@ std::unique_ptr<Setup> make_setup(cyl_plan_t pl, double ka, double eps, bool fli
     upload(s->blocks, s->hblocks);
     s->g16 = env_int("CYLSPEC_ADI_G16", 1) != 0 && !s->hblocks.empty() &&
              std::all_of(s->hblocks.begin(), s->hblocks.end(), [](const BlockDesc& b) { return adi_split_g16(b); });
+    s->z16 = env_int("CYLSPEC_ADI_G16", 1) != 0 && !s->hblocks.empty() &&
+             std::all_of(s->hblocks.begin(), s->hblocks.end(), [](const BlockDesc& b) { return adi_split_gs_z16(b); });
     if (env_int("CYLSPEC_LOG", 0) > 0 && pl->adi_split && !pl->split_gs)
         std::fprintf(stderr, "[cylspec] ADI tables: %zu blocks, %d rows per group in the backward r and the z sweeps\n",
                      s->hblocks.size(), s->g16 ? 16 : 8);
+    if (env_int("CYLSPEC_LOG", 0) > 0 && pl->split_gs)
+        std::fprintf(stderr, "[cylspec] ADI tables: %zu blocks, %d rows per group in the forward z sweeps (state in "
+                             "global memory)\n", s->hblocks.size(), s->z16 ? 16 : 8);
     {
         std::vector<BlockDesc> keep, skip;
         for (const BlockDesc& b : s->hblocks) (b.pr == (std::abs(b.w) & 1) ? keep : skip).push_back(b);
@@ -516,7 +522,7 @@ void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X, bool physica
             hip_check(launch_adi_split_gs(blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
                                           pl->state.as<double>(), pl->state_stride, s->rtab.as<double>(),
                                           s->ztab.as<double>(), s->vmu.as<double>(), pass > 0, pl->lds_bytes,
-                                          pl->stream, nullptr, rp),
+                                          pl->stream, nullptr, rp, s->z16),
                       "adi");
         else if (pl->adi_split)
             hip_check(launch_adi_split(blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
@@ -799,6 +805,9 @@ std::vector<BatchLaunch> build_launches(const std::vector<BlockRef>& refs, int g
         hb.reserve(v.size());
         for (const BlockRef* r : v) hb.push_back(r->b);
         l.g16 = l.kind == 0 && env_int("CYLSPEC_ADI_G16", 1) != 0 && std::all_of(hb.begin(), hb.end(), [](const BlockDesc& b) { return adi_split_g16(b); });
+        if (l.kind == 3)
+            l.g16 = env_int("CYLSPEC_ADI_G16", 1) != 0 &&
+                    std::all_of(hb.begin(), hb.end(), [](const BlockDesc& b) { return adi_split_gs_z16(b); });
         l.blocks = std::make_unique<DevMem>();
         upload(*l.blocks, hb);
         out.push_back(std::move(l));
@@ -814,7 +823,8 @@ void run_adi_launches(hipStream_t st, const std::vector<BatchLaunch>& ls, const 
                                        acc, l.lds, st, pp, nullptr, l.g16), "batched adi");
         else if (l.kind == 3)
             hip_check(launch_adi_split_gs(bl, l.nblocks, l.threads, l.np, nullptr, nullptr, l.state->as<double>(),
-                                          l.state_stride, nullptr, nullptr, nullptr, acc, l.lds, st, pp),
+                                          l.state_stride, nullptr, nullptr, nullptr, acc, l.lds, st, pp, nullptr,
+                                          l.g16),
                       "batched adi");
         else
             hip_check(launch_adi(bl, l.nblocks, l.threads, l.np, nullptr, nullptr,

@@ -146,7 +146,10 @@ hipError_t launch_adi_split_gs(const BlockDesc* blocks, int nblocks, int threads
                                const double* E, double* X, double* state, int64_t state_stride,
                                const double* rtab, const double* ztab, const double* vmu,
                                bool accumulate, size_t lds_bytes, hipStream_t s,
-                               const AdiPtrs* pp = nullptr, const ResArgs* res = nullptr);
+                               const AdiPtrs* pp = nullptr, const ResArgs* res = nullptr, bool z16 = false);
+// z16: groups of 16 columns in the forward z sweeps; every block must satisfy
+// adi_split_gs_z16 (both z halves multiples of 16).
+bool adi_split_gs_z16(const BlockDesc& b);
 // residual: room for the fused residual epilogue's staged tile
 size_t adi_split_gs_lds_bytes(int mp0, int np0, int lines, bool residual);
 int64_t adi_split_gs_state_stride(int mp0, int np0);

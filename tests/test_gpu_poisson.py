@@ -164,13 +164,15 @@ def test_fused_residual_matches_separate_launch(m, n, p):
     assert_close(fused, pb.poisson(f), TOL, "fused residual")
 
 
-@pytest.mark.parametrize("m,n,p", [(256, 256, 4), (192, 192, 6)])
+@pytest.mark.parametrize("m,n,p", [(256, 256, 4), (192, 192, 6), (130, 320, 2)])
 def test_adi_16_row_groups_match_8(m, n, p, capfd):
-    """The LDS split kernel's two instances, 16 rows per group in the backward
-    r and the z sweeps (picked where every block's halves are multiples of 16,
-    as on these grids) and 8 rows everywhere, give bit-identical solutions
-    (grouping changes when loads are issued, not the arithmetic of a row), and
-    they match the oracle."""
+    """The split kernels' two instances give bit-identical solutions (grouping
+    changes when loads are issued, not the arithmetic of a row), and they
+    match the oracle.  LDS-resident state (256 x 256, 192 x 192): 16 rows per
+    group in the backward r and the z sweeps against 8; state in global memory
+    (n_z = 320, z blocks of 159 split 80 + 80): 16 columns per group in the
+    forward z sweeps against 8.  The 16-row instance is picked where every
+    block's halves are multiples of 16, as on these grids."""
     need_gpu()
     banner("adi row groups m=%d n=%d p=%d" % (m, n, p))
     f = smooth_values(m, n, p, S + 43 + m)
