@@ -108,13 +108,22 @@ int cyl_transform_inv(cyl_plan_t plan, const double* coeffs, double* values);
 int cyl_transform_fwd_adjoint(cyl_plan_t plan, const double* coeffs_bar, double* values_bar);
 int cyl_transform_inv_adjoint(cyl_plan_t plan, const double* values_bar, double* coeffs_bar);
 
+/* Build and upload the ADI tables of the Poisson pencil for one tolerance
+ * (Section 3: the eigenvalue bounds, J and the Zolotarev shifts after
+ * Algorithm 1, and the per-shift banded factors).  adi_tol: the ADI tolerance
+ * eps, 1e-15 <= eps <= 1e-2; the number of ADI iterations per mode is
+ * J = ceil(ln(16 gamma) ln(4/eps) / pi^2).  Host work and device allocation;
+ * synchronous.  Preparing a tolerance twice does nothing the second time.
+ * The one- or two-pass policy of the tolerance is fixed here. */
+int cyl_plan_prepare(cyl_plan_t plan, double adi_tol);
+
 /* Solve nabla^2 u = f in the cylinder (Section 3, eq. HelmholtzMatEqn without
  * time terms), u = bc on the boundary (bc_lift == NULL: homogeneous).
  * space: CYL_SPACE_VALUE or CYL_SPACE_COEFF for f, bc_lift and u alike.
- * adi_tol: the ADI tolerance eps, 1e-15 <= eps <= 1e-2; the number of ADI
- * iterations per mode is J = ceil(ln(16 gamma) ln(4/eps) / pi^2).  The first
- * call with a new adi_tol builds and uploads that tolerance's shift tables
- * (host work and device allocation); later calls allocate nothing.
+ * adi_tol: a tolerance prepared with cyl_plan_prepare (CYL_E_INVALID_ARG
+ * otherwise).  Allocates nothing and, with info == NULL, only enqueues
+ * kernels on the plan's stream, so it may be captured into a HIP graph.
+ * Uses the plan's workspace: calls on one plan must not overlap.
  * info: NULL, or a host struct to fill (synchronises; CYL_E_NOT_CONVERGED if
  * the result is not finite or resid_ratio > 1e3 * max(adi_tol, 1e-12)). */
 int cyl_poisson_solve(cyl_plan_t plan, int space, const double* f, const double* bc_lift,
@@ -162,9 +171,8 @@ int cyl_trace_lift(cyl_plan_t plan, const double* rface, const double* zface, do
  * coefficient one banded tau system in r, [A_w Q]_tau x = [R^2 C02 f]_tau,
  * u = Q x, solved directly (no ADI, no tolerance).  space: CYL_SPACE_VALUE or
  * CYL_SPACE_COEFF for f and u alike; in coefficient space u must not alias f.
- * The first call builds the plan's disk records (host work and a small
- * device allocation); later calls allocate nothing.  Timed as the ADI phase
- * when profiling. */
+ * The records are built with the plan; the call allocates nothing.  Timed
+ * as the ADI phase when profiling. */
 int cyl_disk_poisson_solve(cyl_plan_t plan, int space, const double* f, double* u);
 
 /* Heat equation (d_t - alpha nabla^2) T = g (Section 3), advanced by BDF of

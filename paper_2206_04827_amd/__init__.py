@@ -15,7 +15,8 @@ import os
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libcylspec.so")
+# CYLSPEC_LIBRARY: another build of the same library (the host sanitizer build)
+LIB_PATH = os.environ.get("CYLSPEC_LIBRARY") or os.path.join(_PKG, "libcylspec.so")
 
 CYL_OK = 0
 CYL_SPACE_VALUE = 0
@@ -31,7 +32,8 @@ EXPORTS = ["cyl_plan_create", "cyl_plan_destroy", "cyl_transform_fwd", "cyl_tran
            "cyl_transform_fwd_adjoint", "cyl_transform_inv_adjoint", "cyl_heat_grad_create",
            "cyl_heat_grad_forward", "cyl_heat_grad_backward", "cyl_heat_grad_destroy",
            "cyl_batch_create", "cyl_batch_step", "cyl_batch_describe", "cyl_batch_destroy",
-           "cyl_plan_set_physical", "cyl_trace_lift", "cyl_disk_poisson_solve", "cyl_device_peaks"]
+           "cyl_plan_set_physical", "cyl_trace_lift", "cyl_disk_poisson_solve", "cyl_device_peaks",
+           "cyl_plan_prepare"]
 
 CYL_BATCH_NO_GRAPH = 1
 CYL_BATCH_NO_TUNE = 2
@@ -79,6 +81,7 @@ def load():
         "cyl_transform_fwd": [P, P, P],
         "cyl_transform_inv": [P, P, P],
         "cyl_poisson_solve": [P, I, P, P, P, D, ctypes.POINTER(SolveInfo)],
+        "cyl_plan_prepare": [P, D],
         "cyl_heat_create": [ctypes.POINTER(P), P, D, D, I, D, I, ctypes.POINTER(P), P, P],
         "cyl_heat_step": [P, I],
         "cyl_heat_read": [P, I, P],
@@ -157,6 +160,7 @@ class Plan:
             stream = torch.cuda.current_stream()
         self.stream = stream
         self._h = ctypes.c_void_p()
+        self._prepared = set()
         _check(self._lib.cyl_plan_create(ctypes.byref(self._h), self.n_r, self.n_z, self.n_theta,
                                          ctypes.c_void_p(stream.cuda_stream)))
 
@@ -246,12 +250,21 @@ class Plan:
         _check(self._lib.cyl_trace_lift(self._h, _ptr(rface), _ptr(zface), _ptr(out)))
         return out
 
+    def prepare(self, adi_tol):
+        """Build the ADI tables of a tolerance (host work, device allocation)."""
+        adi_tol = float(adi_tol)
+        if adi_tol not in self._prepared:
+            _check(self._lib.cyl_plan_prepare(self._h, adi_tol))
+            self._prepared.add(adi_tol)
+
     def poisson_solve(self, f, bc_lift=None, adi_tol=1e-12, space=None, out=None, info=False,
                       bc_traces=None):
         """Solve nabla^2 u = f (u = lift on the boundary). Returns u (and info if asked).
 
-        bc_traces: (rface, zface) boundary faces instead of a lift (value
-        space); the lift is built with ``trace_lift``."""
+        A tolerance not yet prepared is prepared first (outside graph capture:
+        that allocates).  bc_traces: (rface, zface) boundary faces instead of a
+        lift (value space); the lift is built with ``trace_lift``."""
+        self.prepare(adi_tol)
         if space is None:
             space = CYL_SPACE_COEFF if f.dtype == torch.complex128 else CYL_SPACE_VALUE
         if bc_traces is not None:

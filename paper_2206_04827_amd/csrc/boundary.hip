@@ -49,7 +49,23 @@ __global__ __launch_bounds__(256) void k_zero_blocks(const BlockDesc* __restrict
         Xb[i] = 0.0;
 }
 
+// out[i] = 0 for i < n (grid-stride).  Used instead of hipMemsetAsync so that
+// a captured graph holds kernel nodes only.
+__global__ __launch_bounds__(256) void k_fill_zero(double* __restrict__ out, int64_t n) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_fill_zero(double* out, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t want = (n + 255) / 256;
+    const unsigned grid = static_cast<unsigned>(want < 2048 ? want : 2048);
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid), dim3(256), 0, s, out, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_trace_lift(const double* rface, const double* zface, const double* ra, const double* zb,
                              double* lift, int m, int n, int p, hipStream_t s) {

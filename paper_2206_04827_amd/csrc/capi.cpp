@@ -148,13 +148,14 @@ struct cyl_plan_s {
     int fused_res = 0;             //   emitting the first pass's residual itself (0 never,
                                    //   1 with enough blocks per compute unit, 2 always)
     int num_cus = 0;               // compute units of the device
+    int device = 0;                // the device current when the plan was created
     int64_t state_stride = 0;
     int adi_threads = 64;
     size_t lds_bytes = 0;
-    std::map<std::pair<double, int>, std::unique_ptr<Setup>> setups;
+    std::map<double, std::unique_ptr<Setup>> setups;   // Poisson tables per prepared tolerance
     bool profiling = false;
     bool physical = false;         // Poisson solves keep the j = w (mod 2) blocks only
-    std::unique_ptr<DiskTables> disk;   // horizontal Poisson records (built on first use)
+    std::unique_ptr<DiskTables> disk;   // horizontal Poisson records (built with the plan)
     DevMem disk_lu, disk_taps;
     DevMem lift_ra, lift_zb;       // (1 + r_j)/2, (1 + z_k)/2 of the boundary-trace lift
     struct Rec { int phase; hipEvent_t a, b; };
@@ -340,7 +341,15 @@ std::unique_ptr<Setup> make_setup(cyl_plan_t pl, double ka, double eps, bool fli
     auto s = std::make_unique<Setup>();
     double eps_pass;
     pass_policy(pl->m, pl->n, eps, &s->passes, &eps_pass);
-    s->h = build_adi_setup(pl->geo, pl->rops, pl->zops, ka, eps_pass, flip, pl->adi_split);
+    // test only: CYLSPEC_TEST_BOUNDS_SCALE in (0, 1) shrinks the eigenvalue
+    // bounds so that they no longer enclose the spectrum (drives the residual
+    // check to CYL_E_NOT_CONVERGED without any fault)
+    double a_scale = 1.0;
+    if (const char* t = std::getenv("CYLSPEC_TEST_BOUNDS_SCALE")) {
+        const double v = std::atof(t);
+        if (v > 0.0 && v < 1.0) a_scale = v;
+    }
+    s->h = build_adi_setup(pl->geo, pl->rops, pl->zops, ka, eps_pass, flip, pl->adi_split, a_scale);
     s->flip = flip;
     const Geometry& g = pl->geo;
     const int me0 = g.me[0], me1 = g.me[1], ne0 = g.ne[0], ne1 = g.ne[1];
@@ -405,13 +414,20 @@ std::unique_ptr<Setup> make_setup(cyl_plan_t pl, double ka, double eps, bool fli
     return s;
 }
 
-Setup* poisson_setup(cyl_plan_t pl, double eps) {
-    const auto key = std::make_pair(eps, env_int("CYLSPEC_PASSES", 0));
-    auto it = pl->setups.find(key);
+// The Poisson tables of a tolerance: built (host work, device allocation)
+// by cyl_plan_prepare only; a solve finds them or fails.
+Setup* poisson_setup(cyl_plan_t pl, double eps, bool build) {
+    auto it = pl->setups.find(eps);
     if (it != pl->setups.end()) return it->second.get();
+    if (!build) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "adi_tol %.17g is not prepared on this plan (call cyl_plan_prepare "
+                                        "first; solves allocate nothing)", eps);
+        fail(CYL_E_INVALID_ARG, buf);
+    }
     auto s = make_setup(pl, 0.0, eps);
     Setup* raw = s.get();
-    pl->setups[key] = std::move(s);
+    pl->setups[eps] = std::move(s);
     return raw;
 }
 
@@ -448,11 +464,12 @@ void transform_fwd(cyl_plan_t pl, const double* values, double2* coeffs) {
                          pl->post_fr.as<double>(), pl->fold_r.as<double2>(), pl->stream), "dct_r_fwd");
 }
 
-// coeffs may equal the plan's planesA (in place); coeffs is not modified otherwise.
-void transform_inv(cyl_plan_t pl, const double2* coeffs, double* values) {
+// W: coefficient-plane workspace (nullptr: the plan's planesA); coeffs may
+// equal W (in place) and is not modified otherwise.
+void transform_inv(cyl_plan_t pl, const double2* coeffs, double* values, double2* W = nullptr) {
     Scope sc(pl, PH_INV);
     const Geometry& g = pl->geo;
-    double2* W = pl->planesA.as<double2>();
+    if (!W) W = pl->planesA.as<double2>();
     hip_check(launch_dct(coeffs, W, r_lines(g), g.m, true, pl->dr.view, pl->pre_ir.as<double>(),
                          pl->post_ir.as<double>(), pl->fold_r.as<double2>(), pl->stream), "dct_r_inv");
     hip_check(launch_dct(W, W, z_lines(g), g.n, false, pl->dz.view, pl->pre_iz.as<double>(),
@@ -485,6 +502,29 @@ void transform_inv_adjoint(cyl_plan_t pl, const double* values, double* tmp, dou
     hip_check(launch_scale_planes(coeffs, g.m, g.n, g.p, 1, pl->stream), "scale planes");
 }
 
+// Device workspace of one solve (the plan's own buffers by default).
+struct Work {
+    double2* planesA = nullptr;   // coefficient planes
+    double2* planesB = nullptr;   //   (the lift's, Poisson with bc_lift only)
+    double* E = nullptr;          // right side, E-layout
+    double* X = nullptr;          // solution blocks, X-layout
+    double* R = nullptr;          // residual, E-layout
+    double* acc = nullptr;        // 4 reduction slots
+    double* state = nullptr;      // block state of the HBM/global-state ADI kernels
+};
+
+Work plan_work(cyl_plan_s* pl) {
+    Work w;
+    w.planesA = pl->planesA.as<double2>();
+    w.planesB = pl->planesB.as<double2>();
+    w.E = pl->E.as<double>();
+    w.X = pl->X.as<double>();
+    w.R = pl->R.as<double>();
+    w.acc = pl->acc.as<double>();
+    w.state = pl->state.as<double>();
+    return w;
+}
+
 // Two passes with split kernels: the first pass writes the residual of its
 // own solution (no separate residual launch).  Every round of resident blocks
 // then ends in a burst of E and R traffic; measured, this pays only with at
@@ -497,30 +537,35 @@ bool fuse_residual(const cyl_plan_s* pl, const Setup* s, bool physical) {
 }
 
 // ADI solve of all blocks (physical: the j = w (mod 2) blocks only):
-// X <- solution of A X B + C X D = E (setup pencil).
-void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X, bool physical = false) {
+// X <- solution of A X B + C X D = E (setup pencil).  Residuals go to R,
+// the block state of the global-state kernels to `state` (nullptr: the
+// plan's buffers).
+void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X, bool physical = false,
+               double* R = nullptr, double* state = nullptr) {
     const Geometry& g = pl->geo;
+    if (!R) R = pl->R.as<double>();
+    if (!state) state = pl->state.as<double>();
     const int nblk = physical ? s->n_phys : static_cast<int>(s->hblocks.size());
     DevMem& blocks = physical ? s->blocks_phys : s->blocks;
     const int64_t a_wstride = static_cast<int64_t>(g.me[0] + g.me[1]) * 12;
     const bool fuse = fuse_residual(pl, s, physical);
-    const ResArgs res{pl->R.as<double>(), s->atab.as<double>(), s->ztabA, a_wstride, g.me[0], g.ne[0]};
+    const ResArgs res{R, s->atab.as<double>(), s->ztabA, a_wstride, g.me[0], g.ne[0]};
     for (int pass = 0; pass < s->passes; ++pass) {
         const double* rhs = E;
         if (pass > 0 && fuse) {
-            rhs = pl->R.as<double>();
+            rhs = R;
         } else if (pass > 0) {
             Scope sc(pl, PH_RES);
             hip_check(launch_apply2(blocks.as<BlockDesc>(), nblk, g.me[0], g.ne[0], E, 1.0, X, 1.0, 1.0,
-                                    pl->R.as<double>(), s->atab.as<double>(), a_wstride,
+                                    R, s->atab.as<double>(), a_wstride,
                                     s->ztabA, pl->stream), "residual");
-            rhs = pl->R.as<double>();
+            rhs = R;
         }
         Scope sc(pl, PH_ADI);
         const ResArgs* rp = fuse && pass == 0 ? &res : nullptr;
         if (pl->adi_split && pl->split_gs)
             hip_check(launch_adi_split_gs(blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
-                                          pl->state.as<double>(), pl->state_stride, s->rtab.as<double>(),
+                                          state, pl->state_stride, s->rtab.as<double>(),
                                           s->ztab.as<double>(), s->vmu.as<double>(), pass > 0, pl->lds_bytes,
                                           pl->stream, nullptr, rp, s->z16),
                       "adi");
@@ -531,29 +576,29 @@ void adi_solve(cyl_plan_t pl, Setup* s, const double* E, double* X, bool physica
                       "adi");
         else
             hip_check(launch_adi(blocks.as<BlockDesc>(), nblk, pl->adi_threads, g.np[0], rhs, X,
-                                 pl->state.as<double>(), pl->state_stride, s->rtab.as<double>(),
+                                 state, pl->state_stride, s->rtab.as<double>(),
                                  s->ztab.as<double>(),
                                  s->vmu.as<double>(), pass > 0, pl->use_lds, pl->lds_bytes, pl->stream),
                       "adi");
     }
 }
 
-void check_residual(cyl_plan_t pl, Setup* s, const double* E, const double* X, double eps,
-                    cyl_solve_info* info) {
+// Residual check of a solve (synchronises): R and acc are workspace.
+void check_residual(cyl_plan_t pl, Setup* s, const double* E, const double* X, double* R, double* acc,
+                    double eps, cyl_solve_info* info) {
     const Geometry& g = pl->geo;
     const int nblk = static_cast<int>(s->hblocks.size());
     {
         Scope sc(pl, PH_RES);
         hip_check(launch_apply2(s->blocks.as<BlockDesc>(), nblk, g.me[0], g.ne[0], E, 1.0, X, 1.0, 1.0,
-                                pl->R.as<double>(), s->atab.as<double>(),
+                                R, s->atab.as<double>(),
                                 static_cast<int64_t>(g.me[0] + g.me[1]) * 12,
                                 s->ztabA, pl->stream), "residual");
     }
-    hip_check(hipMemsetAsync(pl->acc.p, 0, 3 * sizeof(double), pl->stream), "memset");
-    hip_check(launch_norms(pl->R.as<double>(), E, g.etotal_elems, X, g.total_elems, pl->acc.as<double>(),
-                           pl->stream), "norms");
+    hip_check(launch_fill_zero(acc, 3, pl->stream), "clear norms");
+    hip_check(launch_norms(R, E, g.etotal_elems, X, g.total_elems, acc, pl->stream), "norms");
     double h[3];
-    hip_check(hipMemcpyAsync(h, pl->acc.p, sizeof(h), hipMemcpyDeviceToHost, pl->stream), "copy norms");
+    hip_check(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, pl->stream), "copy norms");
     hip_check(hipStreamSynchronize(pl->stream), "sync");
     info->J_max = s->h.J_max;
     info->J_min = s->h.J_min;
@@ -668,6 +713,15 @@ void build_plan(cyl_plan_t pl) {
         max_lds = std::max(max_lds, max_lds_sm);
     if (hipDeviceGetAttribute(&pl->num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         pl->num_cus = 0;
+    pl->device = dev;
+    // horizontal (disk) Poisson records: small, built here so that the disk
+    // solve allocates nothing
+    {
+        auto t = std::make_unique<DiskTables>(build_disk_tables(pl->rops, g.nw));
+        upload(pl->disk_lu, t->lu);
+        upload(pl->disk_taps, t->taps);
+        pl->disk = std::move(t);
+    }
     const int mode = env_int("CYLSPEC_ADI_GLOBAL", 0);
     pl->use_lds = mode == 0 && pl->adi_threads <= 256 && g.np[0] <= 128 &&
                   pl->lds_bytes <= static_cast<size_t>(max_lds);
@@ -1011,6 +1065,47 @@ void batch_build(cyl_batch_s* B, int flags) {
     }
 }
 
+// The Poisson solve of Section 3 (eq. HelmholtzMatEqn without time terms) on
+// workspace w: forward transforms, tau right side, ADI (and the residual
+// correction), optional residual check, recombination, inverse transform.
+void poisson_run(cyl_plan_t pl, Setup* s, int space, const double* f, const double* bc_lift, double* u,
+                 double adi_tol, cyl_solve_info* info, const Work& w) {
+    const Geometry& g = pl->geo;
+    const double2* F = reinterpret_cast<const double2*>(f);
+    const double2* Lc = reinterpret_cast<const double2*>(bc_lift);
+    if (space == CYL_SPACE_VALUE) {
+        transform_fwd(pl, f, w.planesA);
+        F = w.planesA;
+        if (bc_lift) {
+            transform_fwd(pl, bc_lift, w.planesB);
+            Lc = w.planesB;
+        }
+    }
+    {
+        Scope sc(pl, PH_RHS);
+        hip_check(launch_rhs3(F, Lc, 1.0, 0.0, -1.0, w.E, s->blocks.as<BlockDesc>(),
+                              pl->plane_of.as<int>(), g.nw, g.m, g.n, pl->rhs, pl->stream), "rhs");
+    }
+    if (pl->physical)
+        hip_check(launch_zero_blocks(s->blocks_skip.as<BlockDesc>(), s->n_skip, g.me[0], g.ne[0], w.X,
+                                     pl->stream), "zero blocks");
+    adi_solve(pl, s, w.E, w.X, pl->physical, w.R, w.state);
+    if (env_int("CYLSPEC_LOG", 0) >= 2)
+        std::fprintf(stderr, "[cylspec] poisson %dx%dx%d tol %.3g: %d blocks, J %d..%d (mean %.2f), %d pass(es)%s%s\n",
+                     pl->m, pl->n, pl->p, adi_tol, pl->physical ? s->n_phys : static_cast<int>(s->hblocks.size()),
+                     s->h.J_min, s->h.J_max, s->h.J_mean, s->passes,
+                     fuse_residual(pl, s, pl->physical) ? ", residual formed by the first pass" : "",
+                     w.E == pl->E.as<double>() ? "" : ", caller workspace");
+    if (info) check_residual(pl, s, w.E, w.X, w.R, w.acc, adi_tol, info);
+    double2* out = space == CYL_SPACE_COEFF ? reinterpret_cast<double2*>(u) : w.planesA;
+    {
+        Scope sc(pl, PH_REC);
+        hip_check(launch_recombine(w.X, Lc, out, pl->plane_of.as<int>(), s->blocks.as<BlockDesc>(), g.nw,
+                                   g.m, g.n, g.p, pl->stream), "recombine");
+    }
+    if (space == CYL_SPACE_VALUE) transform_inv(pl, w.planesA, u, w.planesA);
+}
+
 double* ckpt_slot(cyl_heat_grad_s* a, int j) { return a->ckpt.as<double>() + j * a->ck_stride; }
 double* seg_slot(cyl_heat_grad_s* a, int t) { return a->seg.as<double>() + t * a->heat->plan->geo.total_elems; }
 
@@ -1076,45 +1171,22 @@ int cyl_transform_inv(cyl_plan_t plan, const double* coeffs, double* values) {
     });
 }
 
+int cyl_plan_prepare(cyl_plan_t plan, double adi_tol) {
+    return guarded([&] {
+        if (!plan) fail(CYL_E_INVALID_ARG, "plan is NULL");
+        validate_tol(adi_tol);
+        (void)poisson_setup(plan, adi_tol, true);
+    });
+}
+
 int cyl_poisson_solve(cyl_plan_t plan, int space, const double* f, const double* bc_lift, double* u,
                       double adi_tol, cyl_solve_info* info) {
     return guarded([&] {
         if (!plan || !f || !u) fail(CYL_E_INVALID_ARG, "NULL argument");
         validate_space(space);
         validate_tol(adi_tol);
-        cyl_plan_s* pl = plan;
-        const Geometry& g = pl->geo;
-        Setup* s = poisson_setup(pl, adi_tol);
-        const double2* F = reinterpret_cast<const double2*>(f);
-        const double2* Lc = reinterpret_cast<const double2*>(bc_lift);
-        if (space == CYL_SPACE_VALUE) {
-            transform_fwd(pl, f, pl->planesA.as<double2>());
-            F = pl->planesA.as<double2>();
-            if (bc_lift) {
-                transform_fwd(pl, bc_lift, pl->planesB.as<double2>());
-                Lc = pl->planesB.as<double2>();
-            }
-        }
-        {
-            Scope sc(pl, PH_RHS);
-            hip_check(launch_rhs3(F, Lc, 1.0, 0.0, -1.0, pl->E.as<double>(), s->blocks.as<BlockDesc>(),
-                                  pl->plane_of.as<int>(), g.nw, g.m, g.n, pl->rhs, pl->stream), "rhs");
-        }
-        if (pl->physical) {
-            hip_check(launch_zero_blocks(s->blocks_skip.as<BlockDesc>(), s->n_skip, g.me[0], g.ne[0],
-                                         pl->X.as<double>(), pl->stream), "zero blocks");
-            adi_solve(pl, s, pl->E.as<double>(), pl->X.as<double>(), true);
-        } else {
-            adi_solve(pl, s, pl->E.as<double>(), pl->X.as<double>());
-        }
-        if (info) check_residual(pl, s, pl->E.as<double>(), pl->X.as<double>(), adi_tol, info);
-        double2* out = space == CYL_SPACE_COEFF ? reinterpret_cast<double2*>(u) : pl->planesA.as<double2>();
-        {
-            Scope sc(pl, PH_REC);
-            hip_check(launch_recombine(pl->X.as<double>(), Lc, out, pl->plane_of.as<int>(),
-                                       s->blocks.as<BlockDesc>(), g.nw, g.m, g.n, g.p, pl->stream), "recombine");
-        }
-        if (space == CYL_SPACE_VALUE) transform_inv(pl, pl->planesA.as<double2>(), u);
+        poisson_run(plan, poisson_setup(plan, adi_tol, false), space, f, bc_lift, u, adi_tol, info,
+                    plan_work(plan));
     });
 }
 
@@ -1216,6 +1288,9 @@ int cyl_heat_step(cyl_heat_t h, int n_steps) {
                                           g.etotal_elems, pl->stream), "heat rhs");
             }
             adi_solve(pl, s, pl->E.as<double>(), h->Xt.as<double>(), h->physical);
+            if (env_int("CYLSPEC_LOG", 0) >= 2)
+                std::fprintf(stderr, "[cylspec] heat step %lld of %dx%dx%d: %d blocks, J %d..%d, %d pass(es)\n",
+                             h->steps + 1, pl->m, pl->n, pl->p, nblk, s->h.J_min, s->h.J_max, s->passes);
             // the oldest slot becomes the newest: P_new = C~ Xt B~
             const int slot = (h->head + h->order - 1) % h->order;
             {
@@ -1291,12 +1366,6 @@ int cyl_disk_poisson_solve(cyl_plan_t plan, int space, const double* f, double* 
         if (space == CYL_SPACE_COEFF && f == u) fail(CYL_E_INVALID_ARG, "u must not alias f in coefficient space");
         cyl_plan_s* pl = plan;
         const Geometry& g = pl->geo;
-        if (!pl->disk) {
-            auto t = std::make_unique<DiskTables>(build_disk_tables(pl->rops, g.nw));
-            upload(pl->disk_lu, t->lu);
-            upload(pl->disk_taps, t->taps);
-            pl->disk = std::move(t);
-        }
         const DiskTables& t = *pl->disk;
         const double2* F = reinterpret_cast<const double2*>(f);
         double2* U = reinterpret_cast<double2*>(u);

@@ -179,6 +179,8 @@ hipError_t launch_copy_peak(const double* src, double* dst, int64_t n, int block
 // bound the block sizes.
 hipError_t launch_zero_blocks(const BlockDesc* blocks, int nblocks, int me0, int ne0, double* X,
                               hipStream_t s);
+// out[i] = 0 for i < n, as a kernel (no memset node in a captured graph).
+hipError_t launch_fill_zero(double* out, int64_t n, hipStream_t s);
 
 // out = sE * E - sAB * (A X B) - sCD * (C X D) blockwise.  atab: per (w, r
 // parity) rows of 12 (A row i at i-2..i+3, then C row i at i-2..i+3), w stride

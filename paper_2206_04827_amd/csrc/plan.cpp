@@ -567,10 +567,11 @@ bool adi_split_fits(int me_min, int ne_min) {
 
 void mode_parameters(const DirOps& r, const DirOps& z, int w, double ka, double eps,
                      double zc, double zd, double* bounds4, int* J,
-                     std::vector<double>* u, std::vector<double>* v) {
+                     std::vector<double>* u, std::vector<double>* v, double a_scale) {
     double a, b;
     pencil_bounds_r(radial_A(r, w), r.R2Q, &a, &b);
     if (ka > 0.0) { a -= 1.0 / ka; b -= 1.0 / ka; }
+    if (a_scale != 1.0) a = std::min(a * a_scale, 1.5 * b);   // test only: no longer encloses
     bounds4[0] = a; bounds4[1] = b; bounds4[2] = zc; bounds4[3] = zd;
     *J = adi_num_iterations(a, b, zc, zd, eps);
     if (u && v) {
@@ -580,7 +581,7 @@ void mode_parameters(const DirOps& r, const DirOps& z, int w, double ka, double 
 }
 
 AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, double ka, double eps,
-                         bool flip, bool split) {
+                         bool flip, bool split, double a_scale) {
     AdiSetup s;
     s.kappa_alpha = ka; s.eps = eps; s.nw = g.nw;
     s.split = split;
@@ -610,7 +611,7 @@ AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z, do
     int64_t rsz = 0, zsz = 0, ssz = 0;
     std::vector<std::vector<double>> U(g.nw), V(g.nw);
     parallel_for(g.nw, [&](int w) {
-        mode_parameters(r, z, w, ka, eps, zc, zd, &s.bounds[4 * w], &s.J[w], &U[w], &V[w]);
+        mode_parameters(r, z, w, ka, eps, zc, zd, &s.bounds[4 * w], &s.J[w], &U[w], &V[w], a_scale);
     });
     for (int w = 0; w < g.nw; ++w) {
         s.roff[w] = rsz; s.zoff[w] = zsz; s.soff[w] = ssz;

@@ -147,16 +147,20 @@ Geometry make_geometry(int m, int n, int p);
 // A^T Y B^T + C^T Y D^T = F written for Y~ = J Y J, F~ = J F J inside every
 // parity block, i.e. the pencil (J A^T J, J C^T J), (J B^T J, J D^T J); its
 // spectra, shifts and iteration counts are those of the untransposed pencil.
+// a_scale: test only (1 otherwise): the far end a of the interval enclosing
+// spec(C^-1 A) is multiplied by it, so that a_scale < 1 gives bounds that no
+// longer enclose the spectrum (shifts and J chosen for the wrong interval).
 // split: records for the two-thread sweeps.  A line of n unknowns is cut at
 // t = adi_split_row(n): rows [0, t) are eliminated downwards (LU), rows
 // [t, n) upwards (UL), the lo + hi unknowns around t follow from a small
 // coupling system, and each half then substitutes outwards from t.
 AdiSetup build_adi_setup(const Geometry& g, const DirOps& r, const DirOps& z,
-                         double kappa_alpha, double eps, bool flip = false, bool split = false);
+                         double kappa_alpha, double eps, bool flip = false, bool split = false,
+                         double a_scale = 1.0);
 
 // Bounds/J/shifts of one wavenumber (shared by the setup and the host query).
 void mode_parameters(const DirOps& r, const DirOps& z, int w, double kappa_alpha,
                      double eps, double zc, double zd, double* bounds4, int* J,
-                     std::vector<double>* u, std::vector<double>* v);
+                     std::vector<double>* u, std::vector<double>* v, double a_scale = 1.0);
 
 }  // namespace cyl

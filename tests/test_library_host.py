@@ -51,12 +51,27 @@ def test_plan_create_rejects_sizes(lib, dims, code):
     assert lib.cyl_last_error()
 
 
+def test_plan_create_without_a_device_fails_cleanly(lib):
+    """On a machine without a HIP device, creating a valid plan fails with a
+    HIP or memory status and returns no handle (the partly built plan is
+    freed: the sanitizer build of this test checks that path)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a HIP device is present")
+    h = ctypes.c_void_p()
+    st = lib.cyl_plan_create(ctypes.byref(h), 16, 14, 8, None)
+    assert st in (3, 4), st
+    assert not h.value
+    assert lib.cyl_last_error()
+
+
 def test_null_arguments_are_rejected(lib):
     assert lib.cyl_plan_create(None, 8, 8, 8, None) == 1
     assert lib.cyl_plan_destroy(None) == 1
     assert lib.cyl_transform_fwd(None, None, None) == 1
     assert lib.cyl_transform_inv(None, None, None) == 1
     assert lib.cyl_poisson_solve(None, 0, None, None, None, 1e-12, None) == 1
+    assert lib.cyl_plan_prepare(None, 1e-12) == 1
     h = ctypes.c_void_p()
     assert lib.cyl_heat_create(ctypes.byref(h), None, 1.0, 1e-3, 1, 1e-12, 0, None, None, None) == 1
     assert lib.cyl_heat_step(None, 1) == 1
