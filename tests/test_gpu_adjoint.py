@@ -106,6 +106,30 @@ def test_gradients_with_fused_residual(monkeypatch):
     H.close()
 
 
+def test_gradients_on_global_state_kernel():
+    """Blocks wider than the LDS-resident kernel takes (n above 258): the
+    forward and the transposed (flipped-pencil) heat solves run the split
+    sweeps with the block state in global memory; coefficient-space
+    gradients against the oracle's dense adjoint."""
+    need_gpu()
+    m, n, p, steps, every = 290, 270, 2, 2, 1
+    banner("heat grad global-state kernel %dx%dx%d" % (m, n, p))
+    alpha, h = 0.9, 1e-3
+    h0 = synth.smooth_coeffs(m, n, p, S + 83)
+    hg = synth.smooth_coeffs(m, n, p, S + 84)
+    ht = synth.smooth_coeffs(m, n, p, S + 85)
+    plan = cyl.Plan(m, n, p)
+    H, G, hN, T0b, gb, ab = _run(plan, h0, hg, ht, alpha, h, steps, every, cyl.CYL_SPACE_COEFF)
+    ref = ad.heat_bdf1_grad_coeff(h0, hg, ht, alpha, h, steps, p)
+    assert_close(hN.view(np.float64), ref["h_final"].view(np.float64), TOL, "h_N")
+    assert_close(T0b.view(np.float64), _zero_single_imag(ref["T0_bar"], p).view(np.float64), TOL, "dL/dh0")
+    assert_close(gb.view(np.float64), _zero_single_imag(ref["g_bar"], p).view(np.float64), TOL, "dL/dhg")
+    print("  dL/dalpha %.15e ref %.15e" % (ab, ref["alpha_bar"]), flush=True)
+    assert abs(ab - ref["alpha_bar"]) <= TOL * abs(ref["alpha_bar"])
+    G.close()
+    H.close()
+
+
 def test_gradients_coefficient_space():
     need_gpu()
     m, n, p, steps, every = 16, 14, 6, 4, 3

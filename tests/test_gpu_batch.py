@@ -60,9 +60,12 @@ def test_batch_equals_individual_stepping(graph, tune):
 
 
 def test_batch_member_matches_oracle():
+    """Small members (split, one-thread-per-line and BDF4) and a member on the
+    split sweeps with the block state in global memory (n = 262) against the
+    oracle after 6 batched steps."""
     need_gpu()
     banner("batch member vs oracle")
-    probs = _make([SPECS[0], SPECS[3], SPECS[4]], S + 300)
+    probs = _make([SPECS[0], SPECS[3], SPECS[4], SPECS[6]], S + 300)
     A = _heats(probs)
     batch = cyl.Batch(A)
     batch.step(6)

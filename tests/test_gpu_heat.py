@@ -8,7 +8,8 @@ import paper_2206_04827_amd as cyl
 import synth
 from oracle import problems as pb
 from oracle import transforms as tr
-from tests.gpu_common import S, TOL, assert_close, banner, dev, host, need_gpu, smooth_values
+from tests.gpu_common import (S, TOL, assert_close, assert_slots_close, banner, dev, half_slots, host,
+                               need_gpu, smooth_values)
 
 pytestmark = pytest.mark.gpu
 
@@ -66,11 +67,13 @@ def test_bessel_sine_eigenmode_decay():
     assert np.max(np.abs(got - (1 + h * alpha * lam) ** (-N) * phi)) < 1e-11
 
 
-def test_h128_config_sampled_modes():
+def test_h128_config_all_slots():
     """128^3, alpha = 1, dt = 1e-3, 100 BDF1 steps; T0 = 8 Bessel x sine
-    eigenmodes (seed S+1), g = decaying random forcing (seed S+2)."""
+    eigenmodes (seed S+1), g = decaying random forcing (seed S+2); every
+    Hermitian-half slot against the oracle (one wavenumber per worker)."""
     need_gpu()
-    banner("heat H128 sampled")
+    from tests import oracle_pool
+    banner("heat H128 all slots")
     m = n = p = 128
     prm = synth.eigenmode_params(S + 1)
     T0 = synth.eigenmode_values(prm, m, n, p)
@@ -79,16 +82,44 @@ def test_h128_config_sampled_modes():
     H = cyl.Heat(plan, [dev(T0)], dev(g), 1.0, 1e-3, 1, 1e-12)
     H.step(100)
     got = host(H.read(cyl.CYL_SPACE_COEFF))
-    wn = list(tr.wavenumbers(p))
-    ws = sorted(set([0, 1, 2, int(prm["w"][0]), -64]))      # -64: the Nyquist mode (slot 64)
-    ls = [wn.index(w) for w in ws]
-    slots = [w if w >= 0 else p // 2 for w in ws]
-    cT = tr.forward(T0)
-    cg = tr.forward(g)
-    ref = pb.heat_coeffs([cT], cg, 1.0, 1e-3, 100, order=1, modes=ls)[0]
-    refh = tr.to_half(ref)
-    num = sum(np.linalg.norm(got[s] - refh[s]) ** 2 for s in slots) ** 0.5
-    den = sum(np.linalg.norm(refh[s]) ** 2 for s in slots) ** 0.5
-    mx = max(np.max(np.abs(got[s] - refh[s])) for s in slots) / max(np.max(np.abs(refh[s])) for s in slots)
-    print("  H128 sampled w=%s rel l2 %.3e rel max %.3e" % (ws, num / den, mx), flush=True)
-    assert num / den <= TOL and mx <= TOL
+    ref = oracle_pool.heat_modes([tr.forward(T0)], tr.forward(g), 1.0, 1e-3, 100,
+                                 [l for _, l in half_slots(p)])
+    assert_slots_close(got, ref, p, TOL, "H128")
+
+
+@pytest.mark.parametrize("m,n,p,order,alpha,steps", [(290, 270, 2, 1, 1.0, 3), (262, 262, 4, 4, 0.7, 3)])
+def test_heat_on_global_state_kernel_full_field(m, n, p, order, alpha, steps):
+    """Blocks wider than the LDS-resident kernel takes (n above 258): the
+    split sweeps with the block state in global memory, on the heat pencil
+    (two passes at these sizes), full field against the oracle."""
+    need_gpu()
+    banner("heat global-state kernel %dx%dx%d order %d" % (m, n, p, order))
+    hist = [smooth_values(m, n, p, S + 140 + i) for i in range(order)]
+    g = smooth_values(m, n, p, S + 149)
+    plan = cyl.Plan(m, n, p)
+    H = cyl.Heat(plan, [dev(x) for x in hist], dev(g), alpha, 1e-3, order, 1e-12)
+    H.step(steps)
+    got = host(H.read())
+    ref = pb.heat(hist, g, alpha, 1e-3, steps, order=order)
+    assert_close(got, ref, TOL, "heat %dx%dx%d BDF%d" % (m, n, p, order))
+
+
+def test_b64_member_on_global_state_kernel_matches_oracle():
+    """A member of the 64-problem configuration with n_r = n_z >= 259 (its
+    sizes, diffusivity, initial eigenmodes and forcing), 3 BDF1 steps, every
+    slot against the oracle."""
+    need_gpu()
+    from tests import oracle_pool
+    specs = synth.batch_specs(S + 10)
+    i = min((q for q in range(len(specs)) if specs[q][0] >= 259), key=lambda q: specs[q][2])
+    m, n, p, alpha = specs[i]
+    banner("B64 member %d: %dx%dx%d alpha %.3f" % (i, m, n, p, alpha))
+    T0 = synth.eigenmode_values(synth.eigenmode_params(S + 10 + i), m, n, p)
+    g = smooth_values(m, n, p, S + 100 + i)
+    plan = cyl.Plan(m, n, p)
+    H = cyl.Heat(plan, [dev(T0)], dev(g), alpha, 1e-3, 1, 1e-12)
+    H.step(3)
+    got = host(H.read(cyl.CYL_SPACE_COEFF))
+    ref = oracle_pool.heat_modes([tr.forward(T0)], tr.forward(g), alpha, 1e-3, 3,
+                                 [l for _, l in half_slots(p)])
+    assert_slots_close(got, ref, p, TOL, "B64 member %dx%dx%d" % (m, n, p))
