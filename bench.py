@@ -9,10 +9,15 @@ error against the oracle on the sampled wavenumbers is reported under
 'accuracy' (bar: 1e-10).
 
 Prints one JSON line.  Besides the headline value it carries:
-  roofline      the ADI kernel's FP64 rate against the vector FP64 peak,
-                from HIP events recorded around every ADI launch on the
-                plan's stream inside the timed region;
-  cpu_baseline  the CPU oracle timed on a bounded sample of the same solve;
+  roofline      the ADI kernel's algorithmic FP64 rate (66 flop per interior
+                unknown per iteration) against the vector FP64 peak, from HIP
+                events recorded around every ADI launch on the plan's stream
+                inside the timed region, and its HBM traffic by counters;
+  roofline_model
+                the whole solve against the streaming model (each ADI
+                half-step one HBM round trip);
+  cpu_baseline  the CPU oracle timed on the same solve (all wavenumbers):
+                per-mode solves spread over worker processes, and on one core;
   heat_128      forward BDF1 heat steps per second on the 128^3 grid;
   heat_fwd_adjoint_192
                 forward + adjoint BDF1 heat steps per second at 192^3: 200
@@ -46,15 +51,19 @@ METRIC = ("Poisson unknowns/sec at 256³ FP64 (rel err≤1e-10); "
           "heat fwd+adjoint steps/sec")
 FP64_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
-# FP64 operations per interior unknown per ADI iteration in the kernel's
-# formulation: r-pass 24 (banded product 11, E term 2, forward 4, backward 7),
-# z-pass 14 (forward 2, backward 5, banded product 7).
-ADI_FLOPS_PER_UNKNOWN_ITER = 38.0
-# FP64 operations per unknown of the residual R = E - (A X B + C X D) that the
-# first pass's ADI launch forms when it is fused there: the 6 x 4 window of X
-# against a column of B and of D (48 FMA), the rows of A and C (12 FMA), two
-# subtractions.
-RESIDUAL_FLOPS_PER_UNKNOWN = 122.0
+# Algorithmic FP64 operations per interior unknown per ADI iteration (the
+# streamlined passes of Algorithm 1): r-pass C W (6 diagonals), - E, the
+# (u C - A) LU solve (2 + 3 diagonals and a reciprocal), (v C - A) Y (6), + E
+# and the C solve (2 + 3): about 50; z-pass (v B + D)^-1 (lower 2, upper 1)
+# and (u' B + D) (4 diagonals): about 16.
+ADI_FLOPS_PER_UNKNOWN_ITER = 66.0
+# The kernel's own formulation needs fewer (reported beside): r-pass 24 (one
+# banded product and one LU solve after eliminating the half-step), z-pass 14.
+ADI_KERNEL_FLOPS_PER_UNKNOWN_ITER = 38.0
+# Algorithmic FP64 operations per unknown of the residual
+# R = E - (A X B + C X D) with the parity-split bands A (1,2), C (2,3),
+# B (2,1), D (1,0): A X then (.) B, C X then (.) D (16 FMA), two subtractions.
+RESIDUAL_FLOPS_PER_UNKNOWN = 34.0
 # Streaming model of the solve (each ADI half-step one trip through HBM):
 # bytes per unknown per ADI iteration, and per solve for the transforms, the
 # right side and the recombination (8 passes of 16 B).
@@ -90,8 +99,8 @@ def parse():
     ap.add_argument("--no-small", action="store_true", help="skip the 32^3 latency leg")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=50)
-    ap.add_argument("--cpu-modes", type=int, default=16,
-                    help="wavenumbers the CPU oracle solves in its timed sample")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="worker processes of the all-core CPU oracle leg (capped by the CPU count)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain elementwise kernel reading 512 MiB and writing "
                          "512 MiB (a known-size kernel for scaling FETCH_SIZE / WRITE_SIZE "
@@ -99,67 +108,80 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(m, n, p, seed, nmodes, u_gpu=None):
-    """Time the oracle (numpy/scipy, as it stands) on a bounded sample.
+def _oracle_mode(args):
+    """One wavenumber of the oracle's Poisson solve, BLAS/LAPACK on one thread
+    (runs in a worker process of the CPU baseline)."""
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    from threadpoolctl import threadpool_limits
+    from oracle import problems as pb
+    m, n, w, F = args
+    with threadpool_limits(limits=1):
+        return pb.poisson_mode(m, n, w, F)
 
-    With u_gpu (the GPU solution of the timed loop, host array) also returns
-    its relative error against the oracle on the sampled wavenumbers."""
+
+def _warm(_):
+    """Import the oracle in a worker before the timed map."""
+    from threadpoolctl import threadpool_limits  # noqa: F401
+    from oracle import problems  # noqa: F401
+    return os.getpid()
+
+
+def cpu_baseline(m, n, p, seed, workers, u_gpu=None):
+    """Time the oracle (numpy/scipy, as it stands) on the whole solve.
+
+    The forward and inverse transforms run in this process; the per-mode
+    solves of all p wavenumbers run (a) in `workers` single-threaded worker
+    processes (the value) and (b) here on one thread (single_thread).  With
+    u_gpu (the GPU solution of the timed loop, host array) also returns its
+    relative error against the oracle over all wavenumbers."""
+    import multiprocessing as mp
     import numpy as np
     import synth
+    from threadpoolctl import threadpool_limits
     from oracle import problems as pb
     from oracle import transforms as tr
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    workers = max(1, min(workers, os.cpu_count() or 1))
     h = synth.smooth_coeffs(m, n, p, seed)
     f = tr.inverse(tr.from_half(h, p))
     t0 = time.perf_counter()
     c = tr.forward(f)
     t_fwd = time.perf_counter() - t0
-    ls = list(range(0, p, max(1, p // nmodes)))[:nmodes]
-    t0 = time.perf_counter()
-    U = pb.poisson_coeffs(c, modes=ls)
-    t_modes = time.perf_counter() - t0
+    wn = tr.wavenumbers(p)
+    tasks = [(m, n, int(wn[l]), np.ascontiguousarray(c[l].T)) for l in range(p)]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        pool.map(_warm, range(4 * workers), chunksize=1)     # workers started, oracle imported
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_mode, tasks, chunksize=1)
+        t_pool = time.perf_counter() - t0
+    U = np.stack([x.T for x in res])
     t0 = time.perf_counter()
     tr.inverse(U)
     t_inv = time.perf_counter() - t0
-    t_total = t_fwd + t_inv + t_modes * p / len(ls)
-    # the same oracle with its BLAS/LAPACK limited to one thread (its FFTs are
-    # single-threaded either way), on the first two sampled wavenumbers
-    single = None
-    try:
-        from threadpoolctl import threadpool_limits
-        ls1 = ls[:2]
-        with threadpool_limits(limits=1):
-            t0 = time.perf_counter()
-            pb.poisson_coeffs(c, modes=ls1)
-            t_m1 = time.perf_counter() - t0
-        t1 = t_fwd + t_inv + t_m1 * p / len(ls1)
-        single = {"value": m * n * p / t1, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
-                  "sample": ("the transforms timed above plus the per-mode solves of %d wavenumbers "
-                             "with BLAS/LAPACK on one thread, scaled to all %d; %.2f s measured, "
-                             "%.1f s extrapolated") % (len(ls1), p, t_m1, t1)}
-    except ImportError:
-        pass
+    t_all = t_fwd + t_pool + t_inv
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        U1 = pb.poisson_coeffs(c)
+        t_one = time.perf_counter() - t0
+    t1 = t_fwd + t_one + t_inv
+    assert np.array_equal(U1, U)
     acc = None
     if u_gpu is not None:
         got = tr.forward(u_gpu)
-        num = sum(np.linalg.norm(got[l] - U[l]) ** 2 for l in ls) ** 0.5
-        den = sum(np.linalg.norm(U[l]) ** 2 for l in ls) ** 0.5
-        mx = max(np.max(np.abs(got[l] - U[l])) for l in ls) / max(np.max(np.abs(U[l])) for l in ls)
-        acc = {"rel_l2": num / den, "rel_max": mx, "bar": 1e-10,
-               "wavenumbers": [int(w) for w in tr.wavenumbers(p)[ls]],
-               "reference": "oracle per-mode Bartels-Stewart solves of the cpu_baseline sample"}
-    return acc, {"value": m * n * p / t_total, "unit": "unknowns/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": ("%d^3 Poisson: forward and inverse transforms of the full field timed, "
-                       "per-mode Bartels-Stewart + 2 extended-precision refinements timed on "
-                       "%d of %d wavenumbers (every %d-th) and scaled to all; %.2f s measured, "
-                       "%.1f s extrapolated") % (m, len(ls), p, max(1, p // nmodes),
-                                                 t_fwd + t_inv + t_modes, t_total),
-            "single_thread": single}
+        num = float(np.linalg.norm((got - U).ravel()))
+        den = float(np.linalg.norm(U.ravel()))
+        mx = float(np.max(np.abs(got - U)) / np.max(np.abs(U)))
+        acc = {"rel_l2": num / den, "rel_max": mx, "bar": 1e-10, "wavenumbers": "all %d" % p,
+               "reference": "oracle per-mode Bartels-Stewart solves of the cpu_baseline run"}
+    single = {"value": m * n * p / t1, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+              "sample": ("the whole %d^3 solve on one core: transforms plus the per-mode solves of "
+                         "all %d wavenumbers with BLAS/LAPACK on one thread; %.2f s") % (m, p, t1)}
+    return acc, {"value": m * n * p / t_all, "unit": "unknowns/s", "cores": int(workers), "kind": "oracle",
+                 "sample": ("the whole %d^3 Poisson solve (no extrapolation): forward and inverse "
+                            "transforms in one process (%.2f s), per-mode Bartels-Stewart + 2 "
+                            "extended-precision refinements of all %d wavenumbers in %d single-threaded "
+                            "worker processes (%.2f s)") % (m, t_fwd + t_inv, p, workers, t_pool),
+                 "single_thread": single}
 
 
 def heat_fwd_adjoint(cyl, torch, synth, reps, size=192, steps=200, every=20):
@@ -316,8 +338,10 @@ def main():
     adi_ms = prof["ms_adi"] / n_adi
     passes = info["passes"]
     fused = bool(info["fused_residual"])
-    flops_per_launch = (m - 2) * (n - 2) * p * (ADI_FLOPS_PER_UNKNOWN_ITER * info["adi_iterations_mean"] +
-                                                (RESIDUAL_FLOPS_PER_UNKNOWN / passes if fused else 0.0))
+    interior = (m - 2) * (n - 2) * p
+    flops_per_launch = interior * (ADI_FLOPS_PER_UNKNOWN_ITER * info["adi_iterations_mean"] +
+                                   (RESIDUAL_FLOPS_PER_UNKNOWN / passes if fused else 0.0))
+    kernel_flops = interior * ADI_KERNEL_FLOPS_PER_UNKNOWN_ITER * info["adi_iterations_mean"]
     achieved = flops_per_launch / (adi_ms * 1e-3) / 1e12
     import hashlib
     src = os.path.join(ROOT, "paper_2206_04827_amd", "csrc", "adi.hip")
@@ -329,7 +353,12 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
                 "kernel": "k_adi_split (one ADI pass over all parity blocks%s)" %
                           (", the first also forming the residual" if fused else ""),
-                "avg_launch_ms": round(adi_ms, 4), "launches": n_adi}
+                "avg_launch_ms": round(adi_ms, 4), "launches": n_adi,
+                "flop_per_unknown_iter": ADI_FLOPS_PER_UNKNOWN_ITER,
+                "kernel_formulation_tflops": round(kernel_flops / (adi_ms * 1e-3) / 1e12, 3),
+                "hbm_gbs_from_counters": (round(traffic / (adi_ms * 1e-3) / 1e9, 1) if traffic else None),
+                "hbm_frac_from_counters": (round(traffic / (adi_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                           if traffic else None)}
     phases = {k[3:]: round(prof[k] / args.steps, 4) for k in prof if k.startswith("ms_")}
 
     # the device's own peaks (FP64 FMA chains, streaming copy), measured next
@@ -341,7 +370,7 @@ def main():
     # ADI half-step one HBM round trip (40 B per unknown per iteration: r-pass
     # reads W and E and writes Z, z-pass reads Z and writes W) plus eight
     # transform / right-side / recombination passes of 16 B per unknown; the
-    # FP64 term at the kernel's 38 flop per unknown per iteration
+    # FP64 term at 66 flop per unknown per iteration
     n_unk = float(m * n * p)
     j_total = passes * info["adi_iterations_mean"]
     b_stream = (STREAM_BYTES_PER_UNKNOWN_ITER * j_total + STREAM_PASS_BYTES) * n_unk
@@ -349,7 +378,7 @@ def main():
     t_model = max(b_stream / (HBM_PEAK_GBS * 1e9), f_adi / (FP64_PEAK_TFLOPS * 1e12))
     model = {"model": "streaming ADI (40 B per unknown per iteration) + 8 passes x 16 B per unknown",
              "iterations": round(j_total, 2), "bytes": b_stream, "t_model_ms": round(1e3 * t_model, 4),
-             "t_measured_ms": round(ms_step, 4), "frac_of_hbm_roofline": round(1e3 * t_model / ms_step, 4),
+             "t_measured_ms": round(ms_step, 4), "speed_vs_streaming_model": round(1e3 * t_model / ms_step, 4),
              "frac_vs_measured_copy": round(1e3 * b_stream / (peaks["copy_gbs"] * 1e9) / ms_step, 4),
              "fp64_frac_of_solve": round(f_adi / (ms_step * 1e-3 * FP64_PEAK_TFLOPS * 1e12), 4)}
 
@@ -431,6 +460,15 @@ def main():
                 plan32.poisson_solve(f32, adi_tol=1e-12, out=u32)
             s32.synchronize()
             eager_us = 1e6 * (time.perf_counter() - t0) / reps
+            # phase breakdown (HIP events around every phase; a separate,
+            # untimed loop since the events add host work)
+            plan32.set_profiling(True)
+            plan32.profile()
+            for _ in range(20):
+                plan32.poisson_solve(f32, adi_tol=1e-12, out=u32)
+            pr32 = plan32.profile()
+            plan32.set_profiling(False)
+            phases32 = {k[3:]: round(1e3 * pr32[k] / 20, 2) for k in pr32 if k.startswith("ms_") and pr32[k] > 0}
         g32 = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g32, stream=s32):
             plan32.poisson_solve(f32, adi_tol=1e-12, out=u32)
@@ -443,7 +481,8 @@ def main():
         graph_us = 1e6 * (time.perf_counter() - t0) / reps
         out["poisson_32"] = {"us_per_solve": eager_us, "solves_per_s": 1e6 / eager_us,
                              "unknowns_per_s": ms_ * ns_ * ps_ * 1e6 / eager_us,
-                             "graph_us_per_solve": graph_us, "adi_iterations_max": info32["J_max"],
+                             "graph_us_per_solve": graph_us, "phase_us_per_solve": phases32,
+                             "adi_iterations_max": info32["J_max"],
                              "resid_ratio": info32["resid_ratio"],
                              "config": {"workload": "poisson_32^3_value_space", "adi_tol": 1e-12}}
         del plan32, g32
@@ -502,7 +541,8 @@ def main():
         out["calibration_copy_bytes"] = a.numel() * 8
 
     if not args.no_cpu_baseline:
-        acc, out["cpu_baseline"] = cpu_baseline(m, n, p, synth.SEED_BASE + 3, args.cpu_modes,
+        print("bench: CPU oracle leg", file=sys.stderr, flush=True)
+        acc, out["cpu_baseline"] = cpu_baseline(m, n, p, synth.SEED_BASE + 3, args.cpu_workers,
                                                 u_gpu=u_head.cpu().numpy())
         out["accuracy"] = acc
     print(json.dumps(out), flush=True)
