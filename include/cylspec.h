@@ -129,6 +129,23 @@ int cyl_plan_prepare(cyl_plan_t plan, double adi_tol);
 int cyl_poisson_solve(cyl_plan_t plan, int space, const double* f, const double* bc_lift,
                       double* u, double adi_tol, cyl_solve_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as cyl_poisson_solve, same arguments and results, but its workspace
+ * (coefficient planes, right side, residual, solution blocks and reduction
+ * slots) is carved from a static device array of 64 MiB that the library
+ * holds on every device it runs on until the process ends, instead of the
+ * plan's own buffers.  The call allocates nothing; the plan and the prepared
+ * tolerance must exist beforehand (cyl_plan_create, cyl_plan_prepare).
+ * A grid whose workspace exceeds 64 MiB (about 100^3 values; the lift doubles
+ * the planes) fails with CYL_E_UNSUPPORTED and enqueues nothing.  Every call
+ * on one device shares that device's array, whatever the plan: calls that
+ * may overlap on one device (other streams, other threads) race and must be
+ * ordered by the caller.  The array keeps the last call's contents; the call
+ * clears what it needs cleared itself, with kernels. */
+int cyl_poisson_solve_noalloc(cyl_plan_t plan, int space, const double* f, const double* bc_lift,
+                              double* u, double adi_tol, cyl_solve_info* info);
+
 /* Physical-parity fast path for cyl_poisson_solve on this plan (enable != 0)
  * or the general solve (0, the default).  On the doubled grid (r in [-1, 1])
  * a function that is single-valued and smooth on the cylinder satisfies

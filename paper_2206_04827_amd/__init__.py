@@ -33,7 +33,7 @@ EXPORTS = ["cyl_plan_create", "cyl_plan_destroy", "cyl_transform_fwd", "cyl_tran
            "cyl_heat_grad_forward", "cyl_heat_grad_backward", "cyl_heat_grad_destroy",
            "cyl_batch_create", "cyl_batch_step", "cyl_batch_describe", "cyl_batch_destroy",
            "cyl_plan_set_physical", "cyl_trace_lift", "cyl_disk_poisson_solve", "cyl_device_peaks",
-           "cyl_plan_prepare"]
+           "cyl_plan_prepare", "cyl_poisson_solve_noalloc"]
 
 CYL_BATCH_NO_GRAPH = 1
 CYL_BATCH_NO_TUNE = 2
@@ -82,6 +82,7 @@ def load():
         "cyl_transform_inv": [P, P, P],
         "cyl_poisson_solve": [P, I, P, P, P, D, ctypes.POINTER(SolveInfo)],
         "cyl_plan_prepare": [P, D],
+        "cyl_poisson_solve_noalloc": [P, I, P, P, P, D, ctypes.POINTER(SolveInfo)],
         "cyl_heat_create": [ctypes.POINTER(P), P, D, D, I, D, I, ctypes.POINTER(P), P, P],
         "cyl_heat_step": [P, I],
         "cyl_heat_read": [P, I, P],
@@ -258,12 +259,14 @@ class Plan:
             self._prepared.add(adi_tol)
 
     def poisson_solve(self, f, bc_lift=None, adi_tol=1e-12, space=None, out=None, info=False,
-                      bc_traces=None):
+                      bc_traces=None, noalloc=False):
         """Solve nabla^2 u = f (u = lift on the boundary). Returns u (and info if asked).
 
         A tolerance not yet prepared is prepared first (outside graph capture:
         that allocates).  bc_traces: (rface, zface) boundary faces instead of a
-        lift (value space); the lift is built with ``trace_lift``."""
+        lift (value space); the lift is built with ``trace_lift``.  noalloc:
+        use ``cyl_poisson_solve_noalloc`` (workspace in the library's static
+        device scratch)."""
         self.prepare(adi_tol)
         if space is None:
             space = CYL_SPACE_COEFF if f.dtype == torch.complex128 else CYL_SPACE_VALUE
@@ -275,8 +278,9 @@ class Plan:
         self._check_tensor(bc_lift, space, "bc_lift")
         out = self._out(space, out)
         inf = SolveInfo() if info else None
-        _check(self._lib.cyl_poisson_solve(self._h, space, _ptr(f), _ptr(bc_lift), _ptr(out),
-                                           float(adi_tol), ctypes.byref(inf) if info else None))
+        fn = self._lib.cyl_poisson_solve_noalloc if noalloc else self._lib.cyl_poisson_solve
+        _check(fn(self._h, space, _ptr(f), _ptr(bc_lift), _ptr(out), float(adi_tol),
+                  ctypes.byref(inf) if info else None))
         if info:
             return out, {k: getattr(inf, k) for k, _ in SolveInfo._fields_}
         return out

@@ -13,7 +13,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcylspec.so")
 
 SOURCES = ["plan.cpp", "capi.cpp", "transforms.hip", "adi.hip", "adjoint.hip", "boundary.hip", "disk.hip",
-           "peaks.hip"]
+           "peaks.hip", "scratch.hip"]
 
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

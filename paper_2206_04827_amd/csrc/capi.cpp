@@ -502,7 +502,8 @@ void transform_inv_adjoint(cyl_plan_t pl, const double* values, double* tmp, dou
     hip_check(launch_scale_planes(coeffs, g.m, g.n, g.p, 1, pl->stream), "scale planes");
 }
 
-// Device workspace of one solve (the plan's own buffers by default).
+// Device workspace of one solve: the plan's own buffers, or (the
+// allocation-free entry point) a carve-out of the static scratch.
 struct Work {
     double2* planesA = nullptr;   // coefficient planes
     double2* planesB = nullptr;   //   (the lift's, Poisson with bc_lift only)
@@ -714,6 +715,7 @@ void build_plan(cyl_plan_t pl) {
     if (hipDeviceGetAttribute(&pl->num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         pl->num_cus = 0;
     pl->device = dev;
+    hip_check(scratch_init(dev), "static scratch address");
     // horizontal (disk) Poisson records: small, built here so that the disk
     // solve allocates nothing
     {
@@ -1095,7 +1097,7 @@ void poisson_run(cyl_plan_t pl, Setup* s, int space, const double* f, const doub
                      pl->m, pl->n, pl->p, adi_tol, pl->physical ? s->n_phys : static_cast<int>(s->hblocks.size()),
                      s->h.J_min, s->h.J_max, s->h.J_mean, s->passes,
                      fuse_residual(pl, s, pl->physical) ? ", residual formed by the first pass" : "",
-                     w.E == pl->E.as<double>() ? "" : ", caller workspace");
+                     w.E == pl->E.as<double>() ? "" : ", static scratch");
     if (info) check_residual(pl, s, w.E, w.X, w.R, w.acc, adi_tol, info);
     double2* out = space == CYL_SPACE_COEFF ? reinterpret_cast<double2*>(u) : w.planesA;
     {
@@ -1187,6 +1189,48 @@ int cyl_poisson_solve(cyl_plan_t plan, int space, const double* f, const double*
         validate_tol(adi_tol);
         poisson_run(plan, poisson_setup(plan, adi_tol, false), space, f, bc_lift, u, adi_tol, info,
                     plan_work(plan));
+    });
+}
+
+int cyl_poisson_solve_noalloc(cyl_plan_t plan, int space, const double* f, const double* bc_lift, double* u,
+                              double adi_tol, cyl_solve_info* info) {
+    return guarded([&] {
+        if (!plan || !f || !u) fail(CYL_E_INVALID_ARG, "NULL argument");
+        validate_space(space);
+        validate_tol(adi_tol);
+        cyl_plan_s* pl = plan;
+        Setup* s = poisson_setup(pl, adi_tol, false);
+        const Geometry& g = pl->geo;
+        const size_t planes_bytes = static_cast<size_t>(g.nw) * g.n * g.m * sizeof(double2);
+        const size_t e_bytes = (static_cast<size_t>(g.etotal_elems) + 64) * sizeof(double);
+        const size_t x_bytes = static_cast<size_t>(g.total_elems) * sizeof(double);
+        auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+        const size_t need = up(planes_bytes) * (bc_lift ? 2 : 1) + 2 * up(e_bytes) + up(x_bytes) +
+                            up(4 * sizeof(double)) + up(pl->state.bytes);
+        if (need > kScratchBytes) {
+            char buf[200];
+            std::snprintf(buf, sizeof(buf), "a %dx%dx%d solve needs %zu bytes of workspace; the static scratch of "
+                                            "cyl_poisson_solve_noalloc holds %zu",
+                          pl->m, pl->n, pl->p, need, kScratchBytes);
+            fail(CYL_E_UNSUPPORTED, buf);
+        }
+        char* base = static_cast<char*>(scratch_device_ptr(pl->device));
+        if (!base) fail(CYL_E_INTERNAL, "static scratch address not initialised");
+        Work w;
+        size_t off = 0;
+        auto take = [&](size_t b) { char* q = base + off; off += up(b); return q; };
+        w.planesA = reinterpret_cast<double2*>(take(planes_bytes));
+        if (bc_lift) w.planesB = reinterpret_cast<double2*>(take(planes_bytes));
+        w.E = reinterpret_cast<double*>(take(e_bytes));
+        w.R = reinterpret_cast<double*>(take(e_bytes));
+        w.X = reinterpret_cast<double*>(take(x_bytes));
+        w.acc = reinterpret_cast<double*>(take(4 * sizeof(double)));
+        if (pl->state.bytes) w.state = reinterpret_cast<double*>(take(pl->state.bytes));
+        // the scratch keeps the previous call's contents: the E-layout padding
+        // rows (read by the sweeps, never written) must start at zero
+        hip_check(launch_fill_zero(w.E, static_cast<int64_t>(e_bytes / sizeof(double)), pl->stream), "clear E");
+        hip_check(launch_fill_zero(w.R, static_cast<int64_t>(e_bytes / sizeof(double)), pl->stream), "clear R");
+        poisson_run(pl, s, space, f, bc_lift, u, adi_tol, info, w);
     });
 }
 

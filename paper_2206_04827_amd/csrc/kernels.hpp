@@ -237,4 +237,14 @@ hipError_t launch_scale_planes(double2* U, int m, int n, int p, int mode, hipStr
 hipError_t launch_scale_values(const double* in, double* out, int m, int n, int p, int mode,
                                hipStream_t st);
 
+// ---- static scratch of the allocation-free entry point (scratch.hip) ----
+// Bytes of the file-scope device array: the largest workspace an
+// allocation-free solve may use.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+// Take (once per device, with that device made current) and cache the
+// device address of the scratch array; later calls return at once.
+hipError_t scratch_init(int device);
+// The cached address for `device` (nullptr before scratch_init succeeded).
+void* scratch_device_ptr(int device);
+
 }  // namespace cyl

@@ -71,6 +71,7 @@ def test_null_arguments_are_rejected(lib):
     assert lib.cyl_transform_fwd(None, None, None) == 1
     assert lib.cyl_transform_inv(None, None, None) == 1
     assert lib.cyl_poisson_solve(None, 0, None, None, None, 1e-12, None) == 1
+    assert lib.cyl_poisson_solve_noalloc(None, 0, None, None, None, 1e-12, None) == 1
     assert lib.cyl_plan_prepare(None, 1e-12) == 1
     h = ctypes.c_void_p()
     assert lib.cyl_heat_create(ctypes.byref(h), None, 1.0, 1e-3, 1, 1e-12, 0, None, None, None) == 1
