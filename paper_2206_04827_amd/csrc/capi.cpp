@@ -90,6 +90,7 @@ void upload(DevMem& m, const std::vector<T>& v) {
 
 int env_int(const char* name, int dflt);
 static_assert(kMaxDftPasses == kMaxRadixPasses, "radix plan fits the device view");
+static_assert(kPrimePassOutputs == kPrimeOutputs, "prime pass thread count matches the kernel");
 
 struct DftOwned {
     DftTables t;

@@ -748,8 +748,19 @@ bool dft_radix_plan(int N, std::vector<int>* radices) {
     int c3 = 0, c5 = 0;
     while (n % 3 == 0) { n /= 3; ++c3; }
     while (n % 5 == 0) { n /= 5; ++c5; }
-    // the kernels run such a factor only as the first pass (no twiddles)
-    if (n != 1 || nbig > 1) return false;
+    // one prime factor above 17 (at most kMaxPrimeRadix) is computed directly,
+    // as the first pass, by all threads of a line together (prime_pass)
+    int prime = 0;
+    if (n > 17 && n <= kMaxPrimeRadix) {
+        bool isp = true;
+        for (int d = 2; d * d <= n; ++d)
+            if (n % d == 0) { isp = false; break; }
+        if (isp) { prime = n; n = 1; }
+    }
+    // the kernels run a factor 7, 11, 13 or 17 only as the first pass (no
+    // twiddles), or 7 as the second pass after a prime pass
+    if (n != 1 || nbig > 1 || (prime && big && big != 7)) return false;
+    if (prime) radices->push_back(prime);
     if (big) radices->push_back(big);
     for (int Ls = 1; Ls < p2;) {
         const int rem = p2 / Ls;
@@ -765,13 +776,19 @@ bool dft_radix_plan(int N, std::vector<int>* radices) {
 
 int dft_threads_per_line(int N, const std::vector<int>& radices) {
     int lo = std::max(1, (N + 15) / 16);
-    for (int R : radices)
-        if (R >= 11) lo = std::max(lo, N / R);      // one butterfly per thread
+    for (int R : radices) {
+        if (R > 17) {                               // prime pass: one work item per thread
+            const int ng = (R / 2 + kPrimeOutputs - 1) / kPrimeOutputs;
+            lo = std::max(lo, (N / R) * (ng + 1));
+        } else if (R >= 11) {
+            lo = std::max(lo, N / R);               // one butterfly per thread
+        }
+    }
     int best = lo;
     long long best_cost = -1;
     for (int T = lo; T <= std::max(lo, std::min(N, 2 * lo)); ++T) {
         long long c = 0;
-        for (int R : radices) c += static_cast<long long>((N / R + T - 1) / T) * R;
+        for (int R : radices) c += R > 17 ? 0 : static_cast<long long>((N / R + T - 1) / T) * R;
         c *= T;
         if (best_cost < 0 || c < best_cost) { best_cost = c; best = T; }
     }
@@ -809,6 +826,16 @@ DftTables build_dft_tables(int L, bool mixed) {
                     ++off;
                 }
             Ls *= R;
+        }
+    }
+    // a prime first pass needs no twiddles; its slots hold the roots
+    // (cos, sin)(2 pi m / R), m = 1 .. R-1, that the pass reads
+    if (!t.radices.empty() && t.radices[0] > 17) {
+        const int R = t.radices[0];
+        for (int m = 1; m < R; ++m) {
+            const long double ang = 2.0L * pi * static_cast<long double>(m) / static_cast<long double>(R);
+            t.tw[2 * (m - 1)] = static_cast<double>(std::cos(ang));
+            t.tw[2 * (m - 1) + 1] = static_cast<double>(std::sin(ang));
         }
     }
     if (t.bluestein) {

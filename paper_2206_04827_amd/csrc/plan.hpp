@@ -73,6 +73,10 @@ struct DiskTables {
 DiskTables build_disk_tables(const DirOps& ops, int nw);
 
 constexpr int kMaxRadixPasses = 12;
+// Largest prime radix computed directly (longer prime factors use Bluestein),
+// and the output pairs one thread computes in such a pass.
+constexpr int kMaxPrimeRadix = 257;
+constexpr int kPrimeOutputs = 6;
 // Per-length DFT tables (complex length L; FFT length Nb = L when L factors
 // into the supported radices, else the power of two >= 2L - 1 of Bluestein).
 struct DftTables {
@@ -84,9 +88,10 @@ struct DftTables {
     std::vector<double> bhat;   // 2*Nb: FFT of the Bluestein filter, times 1/Nb
 };
 DftTables build_dft_tables(int L, bool mixed = true);
-// Radix plan of a length-N FFT: an odd prime factor 7, 11, 13 or 17 first
-// (at most one), 16/8/4/2 for the power-of-two part, then 15, 5, 3; false
-// for any other N.
+// Radix plan of a length-N FFT: a prime factor 19..257 first (at most one,
+// computed directly), an odd prime factor 7, 11, 13 or 17 first (at most one;
+// only 7 after a prime pass), 16/8/4/2 for the power-of-two part, then 15, 5,
+// 3; false for any other N.
 bool dft_radix_plan(int N, std::vector<int>* radices);
 // Threads per line for a length-N FFT with the given passes: at least N / 16
 // (and N / R for radices R >= 11), balancing the butterflies of every pass.

@@ -255,6 +255,97 @@ __device__ __forceinline__ void fft_pass(double2* buf, int N, int Ls, const doub
     __syncthreads();
 }
 
+// First pass of a plan led by a prime radix R > 17, too many points for one
+// thread's registers: the N/R sub-transforms (inputs x[b + q nb], q < R,
+// nb = N/R) are computed by the threads of the line together.  Stage 1 forms,
+// in place, a_j = x_j + x_{R-j} and d_j = x_j - x_{R-j} (1 <= j <= R/2).
+// Stage 2 gives each thread one item: kPrimePassOutputs output pairs of one
+// sub-transform,
+//   X_r     = x_0 + sum_j a_j cos(2 pi j r / R) - i sum_j d_j sin(2 pi j r / R),
+//   X_{R-r} = x_0 + sum_j a_j cos(2 pi j r / R) + i sum_j d_j sin(2 pi j r / R),
+// or X_0 = x_0 + sum_j a_j.  The angles j r advance by rotation with
+// exp(2 pi i r / R), restarted from the table every 16 steps (rounding error
+// of at most 16 rotations); roots[m - 1] = (cos, sin)(2 pi m / R).  Outputs
+// go to b R + r (the first Stockham pass).  Needs T >= nb (ceil(H / kPrimePassOutputs) + 1).
+__device__ __forceinline__ void prime_pass(double2* buf, int N, int R, const double2* roots, int t, int T) {
+    constexpr int RB = kPrimePassOutputs;
+    const int nb = N / R, H = R / 2;
+    for (int it = t; it < nb * H; it += T) {
+        const int b = it / H, j = 1 + it % H;
+        const double2 u = buf[P(b + j * nb)], v = buf[P(b + (R - j) * nb)];
+        buf[P(b + j * nb)] = cadd(u, v);
+        buf[P(b + (R - j) * nb)] = csub(u, v);
+    }
+    __syncthreads();
+    const int ng = (H + RB - 1) / RB;
+    double2 oa[RB], od[RB];
+    int ob = -1, r0 = 0, cnt = 0;
+    if (t < nb * (ng + 1)) {
+        const int b = t / (ng + 1), g = t % (ng + 1);
+        const double2* xa = buf;                 // a_j at b + j nb, d_j at b + (R - j) nb
+        const double2 x0 = xa[P(b)];
+        ob = b;
+        if (g == ng) {                           // X_0
+            double2 s0 = x0;
+            for (int j = 1; j <= H; ++j) s0 = cadd(s0, xa[P(b + j * nb)]);
+            oa[0] = s0;
+            r0 = 0;
+            cnt = 1;
+        } else {
+            r0 = 1 + g * RB;
+            cnt = H - r0 + 1 < RB ? H - r0 + 1 : RB;
+            double2 A[RB], B[RB], w[RB], st[RB];
+            int m[RB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                const int r = r0 + i <= H ? r0 + i : r0;    // unused lanes of the item repeat r0
+                A[i] = x0;
+                B[i] = make_double2(0.0, 0.0);
+                st[i] = roots[r - 1];
+                m[i] = 0;
+            }
+            for (int j0 = 1; j0 <= H; j0 += 16) {
+#pragma unroll
+                for (int i = 0; i < RB; ++i) {        // restart: angle j0 r
+                    const int r = r0 + i <= H ? r0 + i : r0;
+                    m[i] = (j0 * r) % R;
+                    w[i] = roots[m[i] - 1];
+                }
+                const int je = j0 + 16 <= H + 1 ? j0 + 16 : H + 1;
+                for (int j = j0; j < je; ++j) {
+                    const double2 a = xa[P(b + j * nb)], d = xa[P(b + (R - j) * nb)];
+#pragma unroll
+                    for (int i = 0; i < RB; ++i) {
+                        A[i] = make_double2(A[i].x + a.x * w[i].x, A[i].y + a.y * w[i].x);
+                        B[i] = make_double2(B[i].x + d.x * w[i].y, B[i].y + d.y * w[i].y);
+                        w[i] = make_double2(w[i].x * st[i].x - w[i].y * st[i].y, w[i].x * st[i].y + w[i].y * st[i].x);
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                oa[i] = make_double2(A[i].x + B[i].y, A[i].y - B[i].x);
+                od[i] = make_double2(A[i].x - B[i].y, A[i].y + B[i].x);
+            }
+        }
+    }
+    __syncthreads();
+    if (ob >= 0) {
+        if (r0 == 0) {
+            buf[P(ob * R)] = oa[0];
+        } else {
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                if (i < cnt) {
+                    buf[P(ob * R + r0 + i)] = oa[i];
+                    buf[P(ob * R + R - r0 - i)] = od[i];
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // In-place forward FFT of the line of d.Nb points in LDS (all threads of the
 // workgroup must call it: it contains barriers), one pass per entry of
 // d.rad.  tw: the per-pass twiddle tables, concatenated in pass order
@@ -271,7 +362,9 @@ __device__ __forceinline__ void fft_lds(double2* buf, const DftDev& d, const dou
         // opaque per pass: keeps the per-radix LDS addresses from being
         // hoisted out of this loop (and spilled across it)
         asm volatile("" : "+v"(t));
-        if (kMixed && p == 0) {
+        if (kMixed && p == 0 && R > 17) {
+            prime_pass(buf, N, R, tw, t, T);
+        } else if (kMixed && p == 0) {
             switch (R) {
                 case 16: fft_pass<16, true>(buf, N, Ls, tw, t, T); break;
                 case 8: fft_pass<8, true>(buf, N, Ls, tw, t, T); break;
@@ -293,6 +386,7 @@ __device__ __forceinline__ void fft_lds(double2* buf, const DftDev& d, const dou
                 case 2: fft_pass<2>(buf, N, Ls, tw, t, T); break;
                 case 3: fft_pass<3>(buf, N, Ls, tw, t, T); break;
                 case 5: fft_pass<5>(buf, N, Ls, tw, t, T); break;
+                case 7: fft_pass<7>(buf, N, Ls, tw, t, T); break;
                 default: fft_pass<15>(buf, N, Ls, tw, t, T); break;
             }
         } else {
@@ -484,7 +578,31 @@ __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, Li
         if (u < t) off = make_double2(off.x + a.x, off.y + a.y);
         F1 = make_double2(F1.x + b.x, F1.y + b.y);
     }
-    if (valid) {
+    if constexpr (!kLineFast) {
+        // threads along a contiguous line: even and odd outputs would leave in
+        // two strided halves (partial cache lines); stage the line in LDS and
+        // write it in order
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < kPts / 2 + 1; ++c) {
+            const int k = t + c * TPL;
+            if (2 * k <= M) {
+                const double sc = 2.0 * post[2 * k];
+                buf[P(2 * k)] = make_double2(sc * ev[c].x, sc * ev[c].y);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kPts / 2 + 1; ++q) {
+            const int k = t * Q + q;
+            if (q < Q && k < Ko) {
+                const double sc = 2.0 * post[2 * k + 1];
+                buf[P(2 * k + 1)] = make_double2(sc * (F1.x + off.x + dk[q].x), sc * (F1.y + off.y + dk[q].y));
+            }
+        }
+        __syncthreads();
+        if (valid)
+            for (int s = t; s <= M; s += TPL) out[base + s * ls.elem] = buf[P(s)];
+    } else if (valid) {
 #pragma unroll
         for (int c = 0; c < kPts / 2 + 1; ++c) {
             const int k = t + c * TPL;

@@ -9,14 +9,17 @@ from tests.gpu_common import banner, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
-# power-of-two, mixed-radix and Bluestein lengths, odd/even/1/2 theta counts,
-# ragged tails.  DFT lengths (r: m - 1, z: n - 1, theta: p) and their passes:
-# 255 = 17 x 15, 17, 34 = 17 x 2; 11, 22 = 11 x 2; 13, 26 = 13 x 2;
-# 7, 35 = 7 x 5, 45 = 15 x 3; 65 = 13 x 5; 39 = 13 x 3; 30 = 2 x 15;
-# 47, 19, 31, 129 = 3 x 43, 119 = 7 x 17 by Bluestein.
+# power-of-two, mixed-radix, prime-pass and Bluestein lengths, odd/even/1/2
+# theta counts, ragged tails.  DFT lengths (r: m - 1, z: n - 1, theta: p) and
+# their passes: 255 = 17 x 15, 17, 34 = 17 x 2; 11, 22 = 11 x 2; 13, 26 =
+# 13 x 2; 7, 35 = 7 x 5, 45 = 15 x 3; 65 = 13 x 5; 39 = 13 x 3; 30 = 2 x 15;
+# direct prime passes 47, 19, 31, 37, 191, 129 = 43 x 3, 511 = 73 x 7,
+# 146 = 73 x 2; Bluestein where no plan exists: 119 = 7 x 17 (two factors of
+# 7 .. 17).
 SIZES = [(4, 4, 1), (8, 6, 4), (9, 7, 5), (17, 33, 16), (33, 20, 12), (32, 32, 32),
          (48, 40, 30), (65, 17, 2), (20, 129, 7), (130, 66, 64), (256, 18, 34),
-         (12, 23, 22), (14, 27, 26), (8, 36, 45), (120, 10, 6)]
+         (12, 23, 22), (14, 27, 26), (8, 36, 45), (120, 10, 6), (10, 9, 37),
+         (192, 40, 6), (24, 192, 2), (512, 20, 4), (30, 512, 3), (8, 8, 146)]
 
 
 @pytest.mark.parametrize("m,n,p", SIZES)
@@ -67,3 +70,26 @@ def test_mixed_radix_equals_bluestein_at_256():
     finally:
         os.environ.pop("CYLSPEC_DFT_MIXED")
     assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("m,n,p", [(512, 40, 4), (192, 96, 6)])
+def test_prime_pass_equals_bluestein(m, n, p):
+    """DFT lengths 511 = 73 x 7 and 191 (prime): the direct prime-radix pass
+    agrees with the Bluestein transforms to rounding, forward and inverse."""
+    import os
+    need_gpu()
+    banner("prime pass vs Bluestein m=%d n=%d p=%d" % (m, n, p))
+    f = np.random.default_rng(m + n).standard_normal((p, n, m))
+    pa = cyl.Plan(m, n, p)
+    a = host(pa.transform_fwd(dev(f)))
+    ia = host(pa.transform_inv(dev(a)))
+    os.environ["CYLSPEC_DFT_MIXED"] = "0"
+    try:
+        pb = cyl.Plan(m, n, p)
+        b = host(pb.transform_fwd(dev(f)))
+        ib = host(pb.transform_inv(dev(a)))
+    finally:
+        os.environ.pop("CYLSPEC_DFT_MIXED")
+    print("  fwd %.3e inv %.3e" % (np.max(np.abs(a - b)) / np.max(np.abs(b)), np.max(np.abs(ia - ib)) / np.max(np.abs(ib))))
+    assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(b))
+    assert np.max(np.abs(ia - ib)) < 1e-13 * np.max(np.abs(ib))
