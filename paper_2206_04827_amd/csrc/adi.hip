@@ -24,6 +24,10 @@
 //             eoff + k * mp + i; rows me..mp-1 are zero.
 //   X-layout  (solutions):                  row-major, element (i, k) at
 //             xoff + i * ne + k.
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "kernels.hpp"
 
 namespace cyl {
@@ -1423,10 +1427,26 @@ hipError_t launch_lds(const BlockDesc* blocks, int nblocks, int threads, const d
     return hipGetLastError();
 }
 
+// The dynamic-LDS limit of a kernel only ever grows: plans of different
+// sizes share the kernel instances, and a smaller plan created later must not
+// lower the limit a larger one launches with (kept per device).
+hipError_t raise_lds_limit(const void* fn, size_t bytes) {
+    int dev = 0;
+    const hipError_t d = hipGetDevice(&dev);
+    if (d != hipSuccess) return d;
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, size_t> set;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& cur = set[{dev, fn}];
+    if (bytes <= cur) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+    if (e == hipSuccess) cur = bytes;
+    return e;
+}
+
 template <int NP>
 hipError_t set_limit(size_t bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_lds<NP>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+    return raise_lds_limit(reinterpret_cast<const void*>(&k_adi_lds<NP>), bytes);
 }
 
 template <int NP>
@@ -1459,20 +1479,16 @@ hipError_t launch_split_gs(const BlockDesc* blocks, int nblocks, int threads, co
 
 template <int NP>
 hipError_t set_split_limit(size_t bytes) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_split<NP, G>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+    const hipError_t e = raise_lds_limit(reinterpret_cast<const void*>(&k_adi_split<NP, G>), bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_split<NP, 16>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+    return raise_lds_limit(reinterpret_cast<const void*>(&k_adi_split<NP, 16>), bytes);
 }
 
 template <int NP>
 hipError_t set_split_gs_limit(size_t bytes) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_split_gs<NP, 8>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+    const hipError_t e = raise_lds_limit(reinterpret_cast<const void*>(&k_adi_split_gs<NP, 8>), bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adi_split_gs<NP, 16>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+    return raise_lds_limit(reinterpret_cast<const void*>(&k_adi_split_gs<NP, 16>), bytes);
 }
 
 }  // namespace
