@@ -24,10 +24,12 @@ and Poisson Equations in a Closed Cylinder", arXiv 2206.04827):
 * ``problems``    -- Poisson and BDF1/BDF4 heat solves on the whole cylinder.
 * ``boundary``    -- the physical parity j = w (mod 2) of smooth fields on the
                      doubled grid, and a transfinite lift from boundary traces.
+* ``pt``          -- the poloidal-toroidal decomposition of Section 4 through
+                     two horizontal (disk) Poisson solves (eq. (ptpoisson)).
 
 Every function cites the section, equation, definition or table it follows.
 Readings of places where the paper is silent, garbled or inconsistent are
 stated where they are used.
 """
 
-from . import operators, transforms, sylvester, adi, problems, adjoint, boundary  # noqa: F401
+from . import operators, transforms, sylvester, adi, problems, adjoint, boundary, pt  # noqa: F401
