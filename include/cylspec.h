@@ -192,6 +192,28 @@ int cyl_trace_lift(cyl_plan_t plan, const double* rface, const double* zface, do
  * as the ADI phase when profiling. */
 int cyl_disk_poisson_solve(cyl_plan_t plan, int space, const double* f, double* u);
 
+/* Poloidal-toroidal decomposition of Section 4 (eqs. pt and ptpoisson):
+ * for V = curl(lambda z) + curl curl(gamma z), z . V = -Delta_h gamma and
+ * z . curl V = -Delta_h lambda.  Given the cylindrical components of V on the
+ * doubled grid (v_r, v_theta, v_z: at (r, theta) with r < 0 the components
+ * along (cos theta, sin theta) and (-sin theta, cos theta) at the point
+ * r (cos theta, sin theta), i.e. with the signed radius), computes
+ *   gamma:  Delta_h gamma  = -v_z,
+ *   lambda: Delta_h lambda = -(z . curl V),
+ * both with the potential zero on the side wall r = 1, by two disk solves
+ * (as cyl_disk_poisson_solve).  The curl enters with r^2 weighting, as the
+ * tau right side [-R (C02 + R C12 D1) V_theta + i w R C02 V_r]_tau, so no
+ * division by r occurs; for even n_theta the theta derivative of the Nyquist
+ * slot w = n_theta/2 is taken as zero.  The field need not be solenoidal.
+ * space: CYL_SPACE_VALUE (all five arrays [n_theta][n_z][n_r] doubles; the
+ * outputs may alias the inputs: all inputs are read first) or
+ * CYL_SPACE_COEFF (all five coefficient planes; lambda must not alias v_r or
+ * v_theta, gamma not v_z).  lambda and gamma must differ.  Enqueued on the
+ * plan's stream; uses the plan's three coefficient-plane buffers and
+ * allocates nothing.  Timed as the ADI phase when profiling. */
+int cyl_pt_decompose(cyl_plan_t plan, int space, const double* v_r, const double* v_theta, const double* v_z,
+                     double* lambda, double* gamma);
+
 /* Heat equation (d_t - alpha nabla^2) T = g (Section 3), advanced by BDF of
  * order bdf_order in {1, 4} with step dt (kappa^(1) = dt,
  * kappa^(4) = 12 dt / 25); g and the boundary data are time independent.

@@ -32,7 +32,7 @@ EXPORTS = ["cyl_plan_create", "cyl_plan_destroy", "cyl_transform_fwd", "cyl_tran
            "cyl_transform_fwd_adjoint", "cyl_transform_inv_adjoint", "cyl_heat_grad_create",
            "cyl_heat_grad_forward", "cyl_heat_grad_backward", "cyl_heat_grad_destroy",
            "cyl_batch_create", "cyl_batch_step", "cyl_batch_describe", "cyl_batch_destroy",
-           "cyl_plan_set_physical", "cyl_trace_lift", "cyl_disk_poisson_solve", "cyl_device_peaks",
+           "cyl_plan_set_physical", "cyl_trace_lift", "cyl_disk_poisson_solve", "cyl_pt_decompose", "cyl_device_peaks",
            "cyl_plan_prepare", "cyl_poisson_solve_noalloc"]
 
 CYL_BATCH_NO_GRAPH = 1
@@ -104,6 +104,7 @@ def load():
         "cyl_plan_set_physical": [P, I],
         "cyl_trace_lift": [P, P, P, P],
         "cyl_disk_poisson_solve": [P, I, P, P],
+        "cyl_pt_decompose": [P, I, P, P, P, P, P],
         "cyl_device_peaks": [P, P, P, ctypes.c_int64, I, ctypes.POINTER(D), ctypes.POINTER(D)],
     }
     for name, args in sig.items():
@@ -293,6 +294,20 @@ class Plan:
         out = self._out(space, out)
         _check(self._lib.cyl_disk_poisson_solve(self._h, space, _ptr(f), _ptr(out)))
         return out
+
+    def pt_decompose(self, v_r, v_theta, v_z, space=None, out=None):
+        """Poloidal-toroidal decomposition (lambda, gamma) of (v_r, v_theta, v_z):
+        Delta_h gamma = -v_z, Delta_h lambda = -(z . curl V), both zero at r = 1."""
+        if space is None:
+            space = CYL_SPACE_COEFF if v_z.dtype == torch.complex128 else CYL_SPACE_VALUE
+        for t, name in ((v_r, "v_r"), (v_theta, "v_theta"), (v_z, "v_z")):
+            self._check_tensor(t, space, name)
+        lam, gam = out if out is not None else (None, None)
+        lam = self._out(space, lam)
+        gam = self._out(space, gam)
+        _check(self._lib.cyl_pt_decompose(self._h, space, _ptr(v_r), _ptr(v_theta), _ptr(v_z),
+                                          _ptr(lam), _ptr(gam)))
+        return lam, gam
 
     def set_profiling(self, enable=True):
         _check(self._lib.cyl_plan_set_profiling(self._h, 1 if enable else 0))

@@ -157,7 +157,8 @@ struct cyl_plan_s {
     bool profiling = false;
     bool physical = false;         // Poisson solves keep the j = w (mod 2) blocks only
     std::unique_ptr<DiskTables> disk;   // horizontal Poisson records (built with the plan)
-    DevMem disk_lu, disk_taps;
+    DevMem disk_lu, disk_taps, disk_pt_taps;
+    DevMem planesC;                // third coefficient-plane buffer (the PT decomposition)
     DevMem lift_ra, lift_zb;       // (1 + r_j)/2, (1 + z_k)/2 of the boundary-trace lift
     struct Rec { int phase; hipEvent_t a, b; };
     std::vector<Rec> recs;
@@ -697,6 +698,7 @@ void build_plan(cyl_plan_t pl) {
     const size_t blk_bytes = static_cast<size_t>(g.total_elems) * sizeof(double);
     pl->planesA.alloc(planes_bytes);
     pl->planesB.alloc(planes_bytes);
+    pl->planesC.alloc(planes_bytes);
     alloc_elayout(pl->E, g);
     pl->X.alloc(blk_bytes);
     alloc_elayout(pl->R, g);
@@ -723,6 +725,7 @@ void build_plan(cyl_plan_t pl) {
         auto t = std::make_unique<DiskTables>(build_disk_tables(pl->rops, g.nw));
         upload(pl->disk_lu, t->lu);
         upload(pl->disk_taps, t->taps);
+        upload(pl->disk_pt_taps, t->pt_taps);
         pl->disk = std::move(t);
     }
     const int mode = env_int("CYLSPEC_ADI_GLOBAL", 0);
@@ -1426,6 +1429,50 @@ int cyl_disk_poisson_solve(cyl_plan_t plan, int space, const double* f, double* 
                       "disk solve");
         }
         if (space == CYL_SPACE_VALUE) transform_inv(pl, pl->planesB.as<double2>(), u);
+    });
+}
+
+int cyl_pt_decompose(cyl_plan_t plan, int space, const double* v_r, const double* v_theta,
+                     const double* v_z, double* lambda, double* gamma) {
+    return guarded([&] {
+        if (!plan || !v_r || !v_theta || !v_z || !lambda || !gamma) fail(CYL_E_INVALID_ARG, "NULL argument");
+        validate_space(space);
+        if (lambda == gamma) fail(CYL_E_INVALID_ARG, "lambda and gamma must be different arrays");
+        if (space == CYL_SPACE_COEFF && (lambda == v_r || lambda == v_theta || gamma == v_z))
+            fail(CYL_E_INVALID_ARG, "in coefficient space lambda must not alias v_r or v_theta, gamma not v_z");
+        cyl_plan_s* pl = plan;
+        const Geometry& g = pl->geo;
+        const DiskTables& t = *pl->disk;
+        const int wnyq = g.p % 2 == 0 ? g.p / 2 : -1;
+        auto disk = [&](const double2* F, double2* U) {
+            Scope sc(pl, PH_ADI);
+            hip_check(launch_disk(F, U, pl->disk_lu.as<double>(), pl->disk_taps.as<double>(), g.m, g.n, g.nw,
+                                  t.rmax, t.rows[0], t.rows[1], pl->stream, -1.0),
+                      "disk solve (gamma)");
+        };
+        auto curl = [&](const double2* Vt, const double2* Vr, double2* U) {
+            Scope sc(pl, PH_ADI);
+            hip_check(launch_disk_pt(Vt, Vr, U, pl->disk_lu.as<double>(), pl->disk_pt_taps.as<double>(), g.m, g.n,
+                                     g.nw, t.rmax, t.rows[0], t.rows[1], wnyq, pl->stream),
+                      "disk solve (lambda)");
+        };
+        if (space == CYL_SPACE_COEFF) {
+            disk(reinterpret_cast<const double2*>(v_z), reinterpret_cast<double2*>(gamma));
+            curl(reinterpret_cast<const double2*>(v_theta), reinterpret_cast<const double2*>(v_r),
+                 reinterpret_cast<double2*>(lambda));
+            return;
+        }
+        double2* A = pl->planesA.as<double2>();
+        double2* B = pl->planesB.as<double2>();
+        double2* C = pl->planesC.as<double2>();
+        // every input is read before an output is written (outputs may alias inputs)
+        transform_fwd(pl, v_r, A);
+        transform_fwd(pl, v_theta, B);
+        curl(B, A, C);
+        transform_fwd(pl, v_z, A);
+        disk(A, B);
+        transform_inv(pl, B, gamma, B);
+        transform_inv(pl, C, lambda, C);
     });
 }
 

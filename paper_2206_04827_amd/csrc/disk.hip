@@ -4,7 +4,8 @@
 // r parity, z coefficient k) one banded tau system in r:
 //   [A_w Q]_tau x = [R^2 C02 f]_tau,   u = Q x   (Q: phi_j = T_(j+2) - T_j),
 // within a parity a (1, 2)-banded no-pivot LU (host-built records) and a
-// 5-tap right side.  One thread per line and parity (real and imaginary parts
+// 5-tap right side.  The poloidal-toroidal decomposition runs the same
+// solve with the curl right side of its lambda potential.  One thread per line and parity (real and imaginary parts
 // together), the two parities of a line in neighbouring lanes.
 #include "kernels.hpp"
 
@@ -22,50 +23,82 @@ constexpr int kDiskRec = 4;    // LU record per row: L, 1/d, U(i,i+1)/d, U(i,i+2
 // as long as a line.  F, U: planes [nw][n][m] complex; U must not alias F.
 // The forward sweep keeps g in U's line, the backward sweep overwrites it
 // with the T coefficients of u behind itself.
-__global__ __launch_bounds__(64) void k_disk(const double2* __restrict__ F, double2* __restrict__ U,
-                                             const double* __restrict__ lu, const double* __restrict__ taps,
-                                             int m, int n, int rmax, int rows0, int rows1) {
+// kPT (poloidal-toroidal decomposition, Section 4): the right side is the
+// r^2-weighted curl -(PTa F) + i w (PTb F2) of F = V_theta, F2 = V_r, whose
+// coefficients of the other r parity feed each row (w taken as 0 in the slot
+// wnyq, the Nyquist mode); otherwise it is scale * (R^2 C02 F).
+template <bool kPT>
+__global__ __launch_bounds__(64) void k_disk(const double2* __restrict__ F, const double2* __restrict__ F2,
+                                             double2* __restrict__ U, const double* __restrict__ lu,
+                                             const double* __restrict__ taps, int m, int n, int rmax,
+                                             int rows0, int rows1, double scale, int wnyq) {
+    constexpr int NT = kPT ? 2 * kDiskTaps : kDiskTaps;   // taps per row
     const int k = blockIdx.x * 32 + (threadIdx.x >> 1);
     const int par = threadIdx.x & 1;
     if (k >= n) return;
     const int w = blockIdx.y;
     const int nr = par ? rows1 : rows0;
+    const int src = kPT ? 1 - par : par;            // r parity of the right side's inputs
     const int64_t line = (static_cast<int64_t>(w) * n + k) * m;
     const double2* f = F + line;
+    const double2* f2 = kPT ? F2 + line : nullptr;
     double2* u = U + line;
-    const double* tp = taps + static_cast<int64_t>(par) * rmax * kDiskTaps;
+    const double* tp = taps + static_cast<int64_t>(par) * rmax * NT;
     const double* rc = lu + (static_cast<int64_t>(w) * 2 + par) * rmax * kDiskRec;
-    auto fc = [&](int q) {
-        const int j = 2 * q + par;
-        return (q >= 0 && j < m) ? f[j] : make_double2(0.0, 0.0);
+    const double wd = (kPT && w != wnyq) ? static_cast<double>(w) : 0.0;
+    auto fc = [&](const double2* a, int q) {
+        const int j = 2 * q + src;
+        return (q >= 0 && j < m) ? a[j] : make_double2(0.0, 0.0);
     };
-    // forward: g_q = b_q - L_q g_(q-1), b_q = sum_s taps_(q,s) f_(q-1+s)
-    double2 fw[kDG + 4];                       // f_(q0-1) .. f_(q0+kDG+2)
+    // forward: g_q = b_q - L_q g_(q-1), b_q from the taps on f_(q-1) .. f_(q+3)
+    double2 fw[kDG + 4], hw[kPT ? kDG + 4 : 1];     // f (and f2) at q0-1 .. q0+kDG+2
 #pragma unroll
-    for (int i = 0; i < kDG + 4; ++i) fw[i] = fc(i - 1);
+    for (int i = 0; i < kDG + 4; ++i) {
+        fw[i] = fc(f, i - 1);
+        if constexpr (kPT) hw[i] = fc(f2, i - 1);
+    }
     double2 g = make_double2(0.0, 0.0);
     for (int q0 = 0; q0 < nr; q0 += kDG) {
-        double2 nx[kDG];
+        double2 nx[kDG], nh[kPT ? kDG : 1];
 #pragma unroll
-        for (int i = 0; i < kDG; ++i) nx[i] = fc(q0 + kDG + 3 + i);
+        for (int i = 0; i < kDG; ++i) {
+            nx[i] = fc(f, q0 + kDG + 3 + i);
+            if constexpr (kPT) nh[i] = fc(f2, q0 + kDG + 3 + i);
+        }
 #pragma unroll
         for (int i = 0; i < kDG; ++i) {
             const int q = q0 + i;
             if (q < nr) {
-                const double* t = tp + q * kDiskTaps;
+                const double* t = tp + q * NT;
                 double2 bq = make_double2(0.0, 0.0);
 #pragma unroll
                 for (int s = 0; s < kDiskTaps; ++s)
                     bq = make_double2(bq.x + t[s] * fw[i + s].x, bq.y + t[s] * fw[i + s].y);
+                if constexpr (kPT) {
+                    double2 cq = make_double2(0.0, 0.0);
+#pragma unroll
+                    for (int s = 0; s < kDiskTaps; ++s)
+                        cq = make_double2(cq.x + t[kDiskTaps + s] * hw[i + s].x,
+                                          cq.y + t[kDiskTaps + s] * hw[i + s].y);
+                    bq = make_double2(-bq.x - wd * cq.y, -bq.y + wd * cq.x);
+                } else {
+                    bq = make_double2(scale * bq.x, scale * bq.y);
+                }
                 const double l = rc[q * kDiskRec];
                 g = make_double2(bq.x - l * g.x, bq.y - l * g.y);
                 u[2 * q + par] = g;
             }
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) fw[i] = fw[i + kDG];
+        for (int i = 0; i < 4; ++i) {
+            fw[i] = fw[i + kDG];
+            if constexpr (kPT) hw[i] = hw[i + kDG];
+        }
 #pragma unroll
-        for (int i = 0; i < kDG; ++i) fw[4 + i] = nx[i];
+        for (int i = 0; i < kDG; ++i) {
+            fw[4 + i] = nx[i];
+            if constexpr (kPT) hw[4 + i] = nh[i];
+        }
     }
     // backward: x_q = g_q / d_q - (U_(q,q+1)/d_q) x_(q+1) - (U_(q,q+2)/d_q) x_(q+2);
     // u_(q+1) = x_q - x_(q+1) (T coefficient 2(q+1) + par), u_par = -x_0
@@ -98,10 +131,21 @@ __global__ __launch_bounds__(64) void k_disk(const double2* __restrict__ F, doub
 }  // namespace
 
 hipError_t launch_disk(const double2* F, double2* U, const double* lu, const double* taps, int m, int n,
-                       int nw, int rmax, int rows0, int rows1, hipStream_t s) {
+                       int nw, int rmax, int rows0, int rows1, hipStream_t s, double scale) {
     if (n == 0 || nw == 0) return hipSuccess;
     const dim3 grid(static_cast<unsigned>((n + 31) / 32), static_cast<unsigned>(nw));
-    hipLaunchKernelGGL(k_disk, grid, dim3(64), 0, s, F, U, lu, taps, m, n, rmax, rows0, rows1);
+    hipLaunchKernelGGL(k_disk<false>, grid, dim3(64), 0, s, F, nullptr, U, lu, taps, m, n, rmax, rows0, rows1,
+                       scale, -1);
+    return hipGetLastError();
+}
+
+hipError_t launch_disk_pt(const double2* Vt, const double2* Vr, double2* U, const double* lu,
+                          const double* pt_taps, int m, int n, int nw, int rmax, int rows0, int rows1, int wnyq,
+                          hipStream_t s) {
+    if (n == 0 || nw == 0) return hipSuccess;
+    const dim3 grid(static_cast<unsigned>((n + 31) / 32), static_cast<unsigned>(nw));
+    hipLaunchKernelGGL(k_disk<true>, grid, dim3(64), 0, s, Vt, Vr, U, lu, pt_taps, m, n, rmax, rows0, rows1,
+                       1.0, wnyq);
     return hipGetLastError();
 }
 

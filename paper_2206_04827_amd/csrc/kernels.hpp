@@ -170,9 +170,17 @@ hipError_t launch_trace_lift(const double* rface, const double* zface, const dou
                              double* lift, int m, int n, int p, hipStream_t s);
 // Horizontal (disk) Poisson (disk.hip): U = disk solve of F, planes
 // [nw][n][m] complex, U not aliasing F; lu [nw][2][rmax][4] and taps
-// [2][rmax][5] as built by build_disk_tables; rows0/rows1: parity row counts.
+// [2][rmax][5] as built by build_disk_tables; rows0/rows1: parity row counts;
+// the right side is scaled by `scale`.
 hipError_t launch_disk(const double2* F, double2* U, const double* lu, const double* taps, int m, int n,
-                       int nw, int rmax, int rows0, int rows1, hipStream_t s);
+                       int nw, int rmax, int rows0, int rows1, hipStream_t s, double scale = 1.0);
+// The lambda solve of the poloidal-toroidal decomposition: U = disk solve of
+// the curl right side of (V_theta, V_r) planes; pt_taps [2][rmax][2][5] as
+// built by build_disk_tables; wnyq: the Nyquist slot (p/2 for even p, else
+// -1), whose theta derivative is taken as zero.  U aliases neither input.
+hipError_t launch_disk_pt(const double2* Vt, const double2* Vr, double2* U, const double* lu,
+                          const double* pt_taps, int m, int n, int nw, int rmax, int rows0, int rows1, int wnyq,
+                          hipStream_t s);
 // Device peak checks (peaks.hip).  launch_fma_peak: `blocks` workgroups of
 // 256 lanes, each running independent FP64 FMA chains for `iters` rounds;
 // *flops receives the launch's FP64 operation count.  launch_copy_peak:

@@ -181,6 +181,8 @@ DirOps build_dir_ops(int n) {
     o.A0f = band_cut(Rad0, n, n);
     o.S10f = o.C02f;
     o.D2f = band_cut(D2, n, n);
+    o.PTa = band_cut(band_mul(R, band_axpby(1.0, S10, 1.0, band_mul(R, band_mul(S1, D1)))), n, n);
+    o.PTb = band_cut(band_mul(R, S10), n, n);
     return o;
 }
 
@@ -883,6 +885,21 @@ DiskTables build_disk_tables(const DirOps& ops, int nw) {
         for (int i = 0; i < t.rows[par]; ++i)
             for (int s = 0; s < kDiskTaps; ++s)
                 t.taps[(static_cast<size_t>(par) * t.rmax + i) * kDiskTaps + s] = Rp[par].get(i, i - 1 + s);
+    // PT curl right side: row i = 2q + par reads the other parity's
+    // coefficients j = 2q' + 1 - par with q' = q - 1 + s, s < kDiskTaps
+    t.pt_taps.assign(2 * static_cast<size_t>(t.rmax) * 2 * kDiskTaps, 0.0);
+    for (int op = 0; op < 2; ++op) {
+        const Band M = band_cut(op == 0 ? ops.PTa : ops.PTb, m - 2, m);
+        for (int i = 0; i < m - 2; ++i)
+            for (int j = 0; j < m; ++j) {
+                const double v = M.get(i, j);
+                if (v == 0.0) continue;
+                const int par = i & 1, q = i >> 1, s = (j >> 1) - (q - 1);
+                if ((j & 1) == par || s < 0 || s >= kDiskTaps)
+                    throw std::logic_error("PT curl right side wider than its taps");
+                t.pt_taps[((static_cast<size_t>(par) * t.rmax + q) * 2 + op) * kDiskTaps + s] = v;
+            }
+    }
     t.lu.assign(static_cast<size_t>(nw) * 2 * t.rmax * kDiskRec, 0.0);
     for (int w = 0; w < nw; ++w) {
         const Band Aw = band_axpby(1.0, ops.A0, -static_cast<double>(w) * w, ops.Cc);

@@ -42,6 +42,10 @@ struct DirOps {
     Band D2Q;  // [D2 Q]_tau                             (z-direction D^T)
     // Full T-coefficient operators, n x n, for right-hand sides and lifts.
     Band R2f, C02f, A0f, S10f, D2f;
+    // Curl right side of the poloidal-toroidal decomposition (Section 4),
+    // n x n, T coefficients -> C^(2): r^2 (z . curl V) =
+    //   PTa V_theta - i w PTb V_r,  PTa = R (C02 + R C12 D1),  PTb = R C02.
+    Band PTa, PTb;
 };
 DirOps build_dir_ops(int n);
 
@@ -69,6 +73,9 @@ struct DiskTables {
     int rows[2] = {0, 0}, cols[2] = {0, 0}, rmax = 0;
     std::vector<double> lu;     // [nw][2][rmax][kDiskRec]
     std::vector<double> taps;   // [2][rmax][kDiskTaps]
+    // PT decomposition: per parity row, taps of PTa then of PTb on the T
+    // coefficients of the other parity, indices q-1 .. q+3 within that parity
+    std::vector<double> pt_taps;   // [2][rmax][2][kDiskTaps]
 };
 DiskTables build_disk_tables(const DirOps& ops, int nw);
 

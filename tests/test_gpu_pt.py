@@ -1,0 +1,93 @@
+"""GPU parity of the poloidal-toroidal decomposition (Section 4, eqs. (pt) and
+(ptpoisson)) against the oracle: full fields at ragged sizes (odd and even
+n_theta, n_theta = 1) in value and coefficient space, the full 256^3 field,
+manufactured potentials recovered exactly, aliasing rules and argument
+errors.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2206_04827_amd as cyl
+import synth
+from oracle import pt
+from oracle import transforms as tr
+from tests.gpu_common import S, TOL, assert_close, banner, dev, host, need_gpu, smooth_values
+from tests.test_oracle_pt import _mesh, _poly, pt_field
+
+pytestmark = pytest.mark.gpu
+
+
+def _fields(m, n, p, seed):
+    return [smooth_values(m, n, p, seed + i) for i in range(3)]
+
+
+@pytest.mark.parametrize("m,n,p", [(6, 5, 3), (12, 9, 6), (17, 13, 7), (33, 20, 12), (64, 40, 1), (130, 66, 10)])
+def test_pt_matches_oracle(m, n, p):
+    need_gpu()
+    banner("pt decomposition m=%d n=%d p=%d" % (m, n, p))
+    v = _fields(m, n, p, S + 300 + m)
+    lam, gam = cyl.Plan(m, n, p).pt_decompose(*[dev(x) for x in v])
+    lr, gr = pt.pt_decompose(*v)
+    assert_close(host(gam), gr, TOL, "gamma")
+    assert_close(host(lam), lr, TOL, "lambda")
+
+
+def test_pt_coefficient_space():
+    need_gpu()
+    m, n, p = 24, 18, 10
+    h = [synth.smooth_coeffs(m, n, p, S + 320 + i) for i in range(3)]
+    lam, gam = cyl.Plan(m, n, p).pt_decompose(*[dev(x) for x in h])
+    lr, gr = pt.pt_decompose_coeffs(*[tr.from_half(x, p) for x in h])
+    assert_close(host(gam), tr.to_half(gr), TOL, "gamma coeff")
+    assert_close(host(lam), tr.to_half(lr), TOL, "lambda coeff")
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_pt_manufactured_potentials_exact(seed):
+    need_gpu()
+    m, n, p = 14, 9, 12
+    rng = np.random.default_rng(200 + seed)
+    lam, gam, vr, vt, vz = pt_field(_poly(rng), _poly(rng), *_mesh(m, n, p))
+    l2, g2 = cyl.Plan(m, n, p).pt_decompose(dev(vr), dev(vt), dev(vz))
+    assert np.max(np.abs(host(g2) - gam)) < 1e-11 * max(1.0, np.max(np.abs(gam)))
+    assert np.max(np.abs(host(l2) - lam)) < 1e-11 * max(1.0, np.max(np.abs(lam)))
+
+
+def test_pt_256_full_field():
+    need_gpu()
+    m = n = p = 256
+    banner("pt decomposition 256^3 full field")
+    v = _fields(m, n, p, S + 340)
+    lam, gam = cyl.Plan(m, n, p).pt_decompose(*[dev(x) for x in v])
+    lam, gam = host(lam), host(gam)
+    torch.cuda.empty_cache()
+    lr, gr = pt.pt_decompose(*v)
+    assert_close(gam, gr, TOL, "gamma 256")
+    assert_close(lam, lr, TOL, "lambda 256")
+
+
+def test_pt_outputs_may_alias_inputs_in_value_space():
+    need_gpu()
+    m, n, p = 20, 14, 8
+    v = _fields(m, n, p, S + 360)
+    plan = cyl.Plan(m, n, p)
+    lam0, gam0 = plan.pt_decompose(*[dev(x) for x in v])
+    a = [dev(x) for x in v]
+    lam1, gam1 = plan.pt_decompose(a[0], a[1], a[2], out=(a[2], a[0]))
+    assert np.array_equal(host(lam1), host(lam0)) and np.array_equal(host(gam1), host(gam0))
+
+
+def test_pt_rejects_bad_aliasing():
+    need_gpu()
+    m, n, p = 10, 8, 4
+    plan = cyl.Plan(m, n, p)
+    h = [dev(synth.smooth_coeffs(m, n, p, S + 380 + i)) for i in range(3)]
+    with pytest.raises(cyl.CylError):
+        plan.pt_decompose(h[0], h[1], h[2], out=(h[1], torch.empty_like(h[2])))
+    with pytest.raises(cyl.CylError):
+        plan.pt_decompose(h[0], h[1], h[2], out=(torch.empty_like(h[0]), h[2]))
+    same = torch.empty_like(h[0])
+    with pytest.raises(cyl.CylError):
+        plan.pt_decompose(h[0], h[1], h[2], out=(same, same))

@@ -99,6 +99,7 @@ def test_null_arguments_are_rejected(lib):
     assert lib.cyl_plan_set_physical(None, 1) == 1
     assert lib.cyl_trace_lift(None, None, None, None) == 1
     assert lib.cyl_disk_poisson_solve(None, 0, None, None) == 1
+    assert lib.cyl_pt_decompose(None, 0, None, None, None, None, None) == 1
     d = ctypes.c_double()
     assert lib.cyl_device_peaks(None, None, None, 16, 0, None, None) == 1        # reps < 1
     assert lib.cyl_device_peaks(None, None, None, 16, 1001, None, None) == 1     # reps > 1000
