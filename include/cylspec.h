@@ -275,14 +275,19 @@ int cyl_heat_grad_destroy(cyl_heat_grad_t a);
  *   (2 E-layout fields each), its own HIP stream and, unless
  *   CYL_BATCH_NO_GRAPH, a HIP graph of one step cycle (lcm of the members'
  *   BDF orders) that cyl_batch_step replays.  Unless CYL_BATCH_NO_TUNE, it
- *   times the candidate launch groupings once (cached per batch signature for
- *   the process) and keeps the fastest.
+ *   times candidate launch configurations once and keeps the fastest: the
+ *   grouping of the blocks into launches, persistent work-queue launches of
+ *   the split kernels, 8- or 16-row groups.  The choice is cached per batch
+ *   signature for the process and, when the environment variable
+ *   CYLSPEC_TUNE_CACHE names a file, in that file (read once per process,
+ *   rewritten whole when an entry is added; an unwritable path only loses
+ *   the cache).
  * cyl_batch_step: advance every member n_steps (enqueue only; ordered after
  *   earlier work on the members' stream and before later work on it).
  *   Members must not be stepped by other calls while in the batch
  *   (CYL_E_INVALID_ARG).  Results are read with cyl_heat_read.
  * cyl_batch_describe: launches per ADI pass, whether a graph is replayed, and
- *   the chosen grouping (a static string owned by the batch). */
+ *   the chosen launch configuration (a string owned by the batch). */
 enum { CYL_BATCH_NO_GRAPH = 1, CYL_BATCH_NO_TUNE = 2 };
 int cyl_batch_create(cyl_batch_t* b, int count, const cyl_heat_t* heats, int flags);
 int cyl_batch_step(cyl_batch_t b, int n_steps);

@@ -405,8 +405,9 @@ class HeatGrad:
 class Batch:
     """Batched stepping of several ``Heat`` handles (uneven sizes) in few launches.
 
-    ``graph``: replay a captured HIP graph of one step cycle; ``tune``: time the
-    candidate launch groupings once and keep the fastest.
+    ``graph``: replay a captured HIP graph of one step cycle; ``tune``: time
+    candidate launch configurations once and keep the fastest (cached per
+    batch signature, on disk when CYLSPEC_TUNE_CACHE names a file).
     """
 
     def __init__(self, heats, graph=True, tune=True):

@@ -918,39 +918,76 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
     }
 }
 
-template <int NP, int GB>
+// Next block of a work-queue launch (kQueue): thread 0 takes the next index
+// from the launch's counter; every thread returns it (>= n: the queue is
+// drained, every wave leaves).  The leading barrier keeps the previous block's
+// LDS use and index reads ahead of the update.
+__device__ __forceinline__ int queue_next(int* counter, int* slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+    __syncthreads();
+    // uniform across the workgroup: keep the block's descriptor in scalar registers
+    return __builtin_amdgcn_readfirstlane(*slot);
+}
+
+// kQueue: a persistent launch over a cost-sorted queue of `nblocks` blocks
+// (grid at most the resident workgroups) of a batch: the per-problem pointer
+// table is required and no residual is formed; otherwise block blockIdx.x.
+template <int NP, int GB, bool kQueue>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_adi_split(const BlockDesc* __restrict__ blocks, const double* __restrict__ E, double* X,
                  const double* __restrict__ rtab, const double* __restrict__ ztab,
                  const double* __restrict__ vmu, int accumulate, const AdiPtrs* __restrict__ pp,
-                 ResArgs res) {
+                 ResArgs res, int* queue, int nblocks) {
     extern __shared__ double sm[];
-    const BlockDesc bd = blocks[blockIdx.x];
-    if (pp != nullptr) {
-        const AdiPtrs q = pp[bd.prob];
-        E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
+    if constexpr (!kQueue) {
+        const BlockDesc bd = blocks[blockIdx.x];
+        if (pp != nullptr) {
+            const AdiPtrs q = pp[bd.prob];
+            E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
+        }
+        adi_block_split<NP + 1, false, GB>(sm, nullptr, bd, E, X, rtab, ztab, vmu, accumulate, res);
+    } else {
+        __shared__ int qslot;
+        for (int b = queue_next(queue, &qslot); b < nblocks; b = queue_next(queue, &qslot)) {
+            const BlockDesc bd = blocks[b];
+            const AdiPtrs q = pp[bd.prob];
+            adi_block_split<NP + 1, false, GB>(sm, nullptr, bd, q.E, q.X, q.rtab, q.ztab, q.vmu, accumulate,
+                                               ResArgs{nullptr, nullptr, nullptr, 0, 0, 0});
+        }
     }
-    adi_block_split<NP + 1, false, GB>(sm, nullptr, bd, E, X, rtab, ztab, vmu, accumulate, res);
 }
 
 // Blocks too large for LDS (n up to 514): split sweeps with the state in
 // global memory, slot blockIdx.x of `state` (state_stride doubles each).
-template <int NP, int GZF>
+// kQueue as for k_adi_split; the state slot is the workgroup's.
+template <int NP, int GZF, bool kQueue>
 __global__ __launch_bounds__(512) void k_adi_split_gs(const BlockDesc* __restrict__ blocks,
                                                       const double* __restrict__ E, double* X,
                                                       double* state, int64_t state_stride,
                                                       const double* __restrict__ rtab,
                                                       const double* __restrict__ ztab,
                                                       const double* __restrict__ vmu, int accumulate,
-                                                      const AdiPtrs* __restrict__ pp, ResArgs res) {
+                                                      const AdiPtrs* __restrict__ pp, ResArgs res, int* queue,
+                                                      int nblocks) {
     extern __shared__ double sm[];
-    const BlockDesc bd = blocks[blockIdx.x];
-    if (pp != nullptr) {
-        const AdiPtrs q = pp[bd.prob];
-        E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
+    double* slot = state + static_cast<int64_t>(blockIdx.x) * state_stride;
+    if constexpr (!kQueue) {
+        const BlockDesc bd = blocks[blockIdx.x];
+        if (pp != nullptr) {
+            const AdiPtrs q = pp[bd.prob];
+            E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
+        }
+        adi_block_split<NP + 1, true, 8, GZF>(sm, slot, bd, E, X, rtab, ztab, vmu, accumulate, res);
+    } else {
+        __shared__ int qslot;
+        for (int b = queue_next(queue, &qslot); b < nblocks; b = queue_next(queue, &qslot)) {
+            const BlockDesc bd = blocks[b];
+            const AdiPtrs q = pp[bd.prob];
+            adi_block_split<NP + 1, true, 8, GZF>(sm, slot, bd, q.E, q.X, q.rtab, q.ztab, q.vmu, accumulate,
+                                                  ResArgs{nullptr, nullptr, nullptr, 0, 0, 0});
+        }
     }
-    adi_block_split<NP + 1, true, 8, GZF>(sm, state + static_cast<int64_t>(blockIdx.x) * state_stride, bd, E, X, rtab,
-                                  ztab, vmu, accumulate, res);
 }
 
 // ---------------------------------------------------------------------------
@@ -1453,13 +1490,24 @@ template <int NP>
 hipError_t launch_split(const BlockDesc* blocks, int nblocks, int threads, const double* E,
                         double* X, const double* rtab, const double* ztab, const double* vmu,
                         bool accumulate, size_t lds_bytes, hipStream_t s, const AdiPtrs* pp,
-                        const ResArgs& res, bool g16) {
-    if (g16)
-        hipLaunchKernelGGL((k_adi_split<NP, 16>), dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
-                           rtab, ztab, vmu, accumulate ? 1 : 0, pp, res);
-    else
-        hipLaunchKernelGGL((k_adi_split<NP, G>), dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
-                           rtab, ztab, vmu, accumulate ? 1 : 0, pp, res);
+                        const ResArgs& res, bool g16, const BlockQueue* q) {
+    const int acc = accumulate ? 1 : 0;
+    if (q != nullptr && (pp == nullptr || q->counter == nullptr)) return hipErrorInvalidValue;
+    if (q != nullptr) {
+        const dim3 grid(static_cast<unsigned>(std::min(q->grid, nblocks)));
+        if (g16)
+            hipLaunchKernelGGL((k_adi_split<NP, 16, true>), grid, dim3(threads), lds_bytes, s, blocks, E, X, rtab,
+                               ztab, vmu, acc, pp, res, q->counter, nblocks);
+        else
+            hipLaunchKernelGGL((k_adi_split<NP, G, true>), grid, dim3(threads), lds_bytes, s, blocks, E, X, rtab,
+                               ztab, vmu, acc, pp, res, q->counter, nblocks);
+    } else if (g16) {
+        hipLaunchKernelGGL((k_adi_split<NP, 16, false>), dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
+                           rtab, ztab, vmu, acc, pp, res, nullptr, nblocks);
+    } else {
+        hipLaunchKernelGGL((k_adi_split<NP, G, false>), dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
+                           rtab, ztab, vmu, acc, pp, res, nullptr, nblocks);
+    }
     return hipGetLastError();
 }
 
@@ -1467,28 +1515,51 @@ template <int NP>
 hipError_t launch_split_gs(const BlockDesc* blocks, int nblocks, int threads, const double* E, double* X,
                            double* state, int64_t state_stride, const double* rtab, const double* ztab,
                            const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
-                           const AdiPtrs* pp, const ResArgs& res, bool z16) {
-    if (z16)
-        hipLaunchKernelGGL((k_adi_split_gs<NP, 16>), dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
-                           state, state_stride, rtab, ztab, vmu, accumulate ? 1 : 0, pp, res);
-    else
-        hipLaunchKernelGGL((k_adi_split_gs<NP, 8>), dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E, X,
-                           state, state_stride, rtab, ztab, vmu, accumulate ? 1 : 0, pp, res);
+                           const AdiPtrs* pp, const ResArgs& res, bool z16, const BlockQueue* q) {
+    const int acc = accumulate ? 1 : 0;
+    if (q != nullptr && (pp == nullptr || q->counter == nullptr)) return hipErrorInvalidValue;
+    if (q != nullptr) {
+        const dim3 grid(static_cast<unsigned>(std::min(q->grid, nblocks)));
+        if (z16)
+            hipLaunchKernelGGL((k_adi_split_gs<NP, 16, true>), grid, dim3(threads), lds_bytes, s, blocks, E, X,
+                               state, state_stride, rtab, ztab, vmu, acc, pp, res, q->counter, nblocks);
+        else
+            hipLaunchKernelGGL((k_adi_split_gs<NP, 8, true>), grid, dim3(threads), lds_bytes, s, blocks, E, X,
+                               state, state_stride, rtab, ztab, vmu, acc, pp, res, q->counter, nblocks);
+    } else if (z16) {
+        hipLaunchKernelGGL((k_adi_split_gs<NP, 16, false>), dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E,
+                           X, state, state_stride, rtab, ztab, vmu, acc, pp, res, nullptr, nblocks);
+    } else {
+        hipLaunchKernelGGL((k_adi_split_gs<NP, 8, false>), dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E,
+                           X, state, state_stride, rtab, ztab, vmu, acc, pp, res, nullptr, nblocks);
+    }
     return hipGetLastError();
 }
 
 template <int NP>
 hipError_t set_split_limit(size_t bytes) {
-    const hipError_t e = raise_lds_limit(reinterpret_cast<const void*>(&k_adi_split<NP, G>), bytes);
-    if (e != hipSuccess) return e;
-    return raise_lds_limit(reinterpret_cast<const void*>(&k_adi_split<NP, 16>), bytes);
+    const void* fns[4] = {reinterpret_cast<const void*>(&k_adi_split<NP, G, false>),
+                          reinterpret_cast<const void*>(&k_adi_split<NP, 16, false>),
+                          reinterpret_cast<const void*>(&k_adi_split<NP, G, true>),
+                          reinterpret_cast<const void*>(&k_adi_split<NP, 16, true>)};
+    for (const void* f : fns) {
+        const hipError_t e = raise_lds_limit(f, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int NP>
 hipError_t set_split_gs_limit(size_t bytes) {
-    const hipError_t e = raise_lds_limit(reinterpret_cast<const void*>(&k_adi_split_gs<NP, 8>), bytes);
-    if (e != hipSuccess) return e;
-    return raise_lds_limit(reinterpret_cast<const void*>(&k_adi_split_gs<NP, 16>), bytes);
+    const void* fns[4] = {reinterpret_cast<const void*>(&k_adi_split_gs<NP, 8, false>),
+                          reinterpret_cast<const void*>(&k_adi_split_gs<NP, 16, false>),
+                          reinterpret_cast<const void*>(&k_adi_split_gs<NP, 8, true>),
+                          reinterpret_cast<const void*>(&k_adi_split_gs<NP, 16, true>)};
+    for (const void* f : fns) {
+        const hipError_t e = raise_lds_limit(f, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -1529,11 +1600,11 @@ size_t adi_split_lds_bytes(int mp0, int np0) {
 hipError_t launch_adi_split(const BlockDesc* blocks, int nblocks, int threads, int np0,
                             const double* E, double* X, const double* rtab, const double* ztab,
                             const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
-                            const AdiPtrs* pp, const ResArgs* res, bool g16) {
+                            const AdiPtrs* pp, const ResArgs* res, bool g16, const BlockQueue* q) {
     if (threads < 128 || threads > 256 || threads % 128 != 0) return hipErrorInvalidValue;
     const ResArgs ra = res ? *res : ResArgs{nullptr, nullptr, nullptr, 0, 0, 0};
     switch (np0) {
-#define CYL_CASE(v) case v: return launch_split<v>(blocks, nblocks, threads, E, X, rtab, ztab, vmu, accumulate, lds_bytes, s, pp, ra, g16);
+#define CYL_CASE(v) case v: return launch_split<v>(blocks, nblocks, threads, E, X, rtab, ztab, vmu, accumulate, lds_bytes, s, pp, ra, g16, q);
         CYL_NP_CASES(CYL_CASE)
 #undef CYL_CASE
         default: return hipErrorInvalidValue;
@@ -1561,12 +1632,52 @@ hipError_t launch_adi_split_gs(const BlockDesc* blocks, int nblocks, int threads
                                const double* E, double* X, double* state, int64_t state_stride,
                                const double* rtab, const double* ztab, const double* vmu,
                                bool accumulate, size_t lds_bytes, hipStream_t s, const AdiPtrs* pp,
-                               const ResArgs* res, bool z16) {
+                               const ResArgs* res, bool z16, const BlockQueue* q) {
     if (threads < 128 || threads > 512 || threads % 128 != 0) return hipErrorInvalidValue;
     const ResArgs ra = res ? *res : ResArgs{nullptr, nullptr, nullptr, 0, 0, 0};
     switch (np0) {
-#define CYL_CASE(v) case v: return launch_split_gs<v>(blocks, nblocks, threads, E, X, state, state_stride, rtab, ztab, vmu, accumulate, lds_bytes, s, pp, ra, z16);
+#define CYL_CASE(v) case v: return launch_split_gs<v>(blocks, nblocks, threads, E, X, state, state_stride, rtab, ztab, vmu, accumulate, lds_bytes, s, pp, ra, z16, q);
         CYL_NP_GS_CASES(CYL_CASE)
+#undef CYL_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+namespace {
+template <typename K>
+hipError_t resident_grid(K kernel, int threads, size_t lds, int* grid) {
+    int dev = 0, cus = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(kernel), threads, lds);
+    if (e == hipSuccess) *grid = cus * (per > 0 ? per : 1);
+    return e;
+}
+template <int NP>
+hipError_t queue_grid_gs(int threads, size_t lds, bool g16, int* grid) {
+    return g16 ? resident_grid(&k_adi_split_gs<NP, 16, true>, threads, lds, grid)
+               : resident_grid(&k_adi_split_gs<NP, 8, true>, threads, lds, grid);
+}
+template <int NP>
+hipError_t queue_grid_lds(int threads, size_t lds, bool g16, int* grid) {
+    return g16 ? resident_grid(&k_adi_split<NP, 16, true>, threads, lds, grid)
+               : resident_grid(&k_adi_split<NP, G, true>, threads, lds, grid);
+}
+}  // namespace
+
+hipError_t adi_split_queue_grid(int np0, int threads, size_t lds, bool gs, bool g16, int* grid) {
+    if (gs) {
+        switch (np0) {
+#define CYL_CASE(v) case v: return queue_grid_gs<v>(threads, lds, g16, grid);
+            CYL_NP_GS_CASES(CYL_CASE)
+#undef CYL_CASE
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (np0) {
+#define CYL_CASE(v) case v: return queue_grid_lds<v>(threads, lds, g16, grid);
+        CYL_NP_CASES(CYL_CASE)
 #undef CYL_CASE
         default: return hipErrorInvalidValue;
     }

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -17,6 +18,8 @@
 #include <stdexcept>
 #include <string>
 #include <vector>
+
+#include <unistd.h>
 
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -201,7 +204,29 @@ struct BatchLaunch {
     int nblocks = 0;
     int64_t state_stride = 0;
     bool g16 = false;             // 16-row groups: LDS split (kind 0) or forward z of the global-state split (kind 3)
-    std::unique_ptr<cyl::DevMem> blocks, state;
+    bool queue = false;           // split kinds: persistent workgroups over a work queue
+    int grid = 0;                 //   and their number (resident at once)
+    std::unique_ptr<cyl::DevMem> blocks, state, counter;
+};
+
+// Launch configuration of a batch's ADI passes (chosen by the tuner).
+struct BatchCfg {
+    int grouping = 0;             // 0 per (kernel, threads), 1 per (kernel, threads, width), 2 per kernel
+    bool queue = false;           // work-queue launches of the split kernels
+    bool g16 = true;              // 16-row groups where every block allows them
+    std::string str() const {
+        return "g" + std::to_string(grouping) + (queue ? "q1" : "q0") + (g16 ? "s16" : "s8");
+    }
+    static bool parse(const std::string& t, BatchCfg* c) {
+        int g = -1, q = -1, sz = -1;
+        if (std::sscanf(t.c_str(), "g%dq%ds%d", &g, &q, &sz) != 3 || g < 0 || g > 2 || (q != 0 && q != 1) ||
+            (sz != 8 && sz != 16))
+            return false;
+        c->grouping = g;
+        c->queue = q == 1;
+        c->g16 = sz == 16;
+        return true;
+    }
 };
 
 // Batched heat stepping over independent problems (uneven sizes).
@@ -821,7 +846,8 @@ struct BlockRef {
 // 1: one per (kernel, threads, padded width); 2: one per kernel.  Blocks of a
 // launch are sorted by cost (J me ne) so that the dispatcher hands the
 // longest blocks out first.
-std::vector<BatchLaunch> build_launches(const std::vector<BlockRef>& refs, int grouping) {
+std::vector<BatchLaunch> build_launches(const std::vector<BlockRef>& refs, const BatchCfg& cfg) {
+    const int grouping = cfg.grouping;
     std::map<std::tuple<int, int, int>, std::vector<const BlockRef*>> groups;
     for (const auto& r : refs) {
         const std::tuple<int, int, int> key =
@@ -864,10 +890,21 @@ std::vector<BatchLaunch> build_launches(const std::vector<BlockRef>& refs, int g
         std::vector<BlockDesc> hb;
         hb.reserve(v.size());
         for (const BlockRef* r : v) hb.push_back(r->b);
-        l.g16 = l.kind == 0 && env_int("CYLSPEC_ADI_G16", 1) != 0 && std::all_of(hb.begin(), hb.end(), [](const BlockDesc& b) { return adi_split_g16(b); });
+        const bool g16_ok = cfg.g16 && env_int("CYLSPEC_ADI_G16", 1) != 0;
+        l.g16 = l.kind == 0 && g16_ok && std::all_of(hb.begin(), hb.end(), [](const BlockDesc& b) { return adi_split_g16(b); });
         if (l.kind == 3)
-            l.g16 = env_int("CYLSPEC_ADI_G16", 1) != 0 &&
-                    std::all_of(hb.begin(), hb.end(), [](const BlockDesc& b) { return adi_split_gs_z16(b); });
+            l.g16 = g16_ok && std::all_of(hb.begin(), hb.end(), [](const BlockDesc& b) { return adi_split_gs_z16(b); });
+        if (cfg.queue && (l.kind == 0 || l.kind == 3)) {
+            l.queue = true;
+            hip_check(adi_split_queue_grid(l.np, l.threads, l.lds, l.kind == 3, l.g16, &l.grid), "queue grid");
+            l.grid = std::max(1, std::min(l.grid, l.nblocks));
+            l.counter = std::make_unique<DevMem>();
+            l.counter->alloc(sizeof(double));
+            if (l.kind == 3) {      // one state slot per persistent workgroup
+                l.state = std::make_unique<DevMem>();
+                l.state->alloc(static_cast<size_t>(l.grid) * l.state_stride * sizeof(double));
+            }
+        }
         l.blocks = std::make_unique<DevMem>();
         upload(*l.blocks, hb);
         out.push_back(std::move(l));
@@ -878,13 +915,19 @@ std::vector<BatchLaunch> build_launches(const std::vector<BlockRef>& refs, int g
 void run_adi_launches(hipStream_t st, const std::vector<BatchLaunch>& ls, const AdiPtrs* pp, bool acc) {
     for (const auto& l : ls) {
         const BlockDesc* bl = l.blocks->as<BlockDesc>();
+        BlockQueue q{nullptr, l.grid};
+        if (l.queue) {
+            // the counter starts at zero (a fill kernel: capturable, unlike a memset node)
+            hip_check(launch_fill_zero(l.counter->as<double>(), 1, st), "queue reset");
+            q.counter = l.counter->as<int>();
+        }
         if (l.kind == 0)
             hip_check(launch_adi_split(bl, l.nblocks, l.threads, l.np, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                       acc, l.lds, st, pp, nullptr, l.g16), "batched adi");
+                                       acc, l.lds, st, pp, nullptr, l.g16, l.queue ? &q : nullptr), "batched adi");
         else if (l.kind == 3)
             hip_check(launch_adi_split_gs(bl, l.nblocks, l.threads, l.np, nullptr, nullptr, l.state->as<double>(),
                                           l.state_stride, nullptr, nullptr, nullptr, acc, l.lds, st, pp, nullptr,
-                                          l.g16),
+                                          l.g16, l.queue ? &q : nullptr),
                       "batched adi");
         else
             hip_check(launch_adi(bl, l.nblocks, l.threads, l.np, nullptr, nullptr,
@@ -919,14 +962,57 @@ void batch_advance(cyl_batch_s* B) {
 }
 
 std::mutex g_tune_mutex;
-std::map<std::string, int> g_tune_cache;
+std::map<std::string, std::string> g_tune_cache;   // batch signature -> BatchCfg::str()
+bool g_tune_file_read = false;
 
-// Time one pass-1 ADI with each grouping on scratch outputs; keep the fastest.
-int autotune_grouping(cyl_batch_s* B, const std::vector<BlockRef>& refs, const std::string& key) {
+// The on-disk tuning cache (CYLSPEC_TUNE_CACHE = path; none when unset):
+// one "signature<TAB>configuration" line per tuned batch.  Read once per
+// process; rewritten whole (temporary file, then rename) when an entry is
+// added.  Callers hold g_tune_mutex.
+std::string tune_file() {
+    const char* f = std::getenv("CYLSPEC_TUNE_CACHE");
+    return f ? std::string(f) : std::string();
+}
+void tune_file_read() {
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const std::string path = tune_file();
+    if (path.empty()) return;
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+        const size_t tab = line.find('\t');
+        BatchCfg c;
+        if (tab != std::string::npos && BatchCfg::parse(line.substr(tab + 1), &c))
+            g_tune_cache.emplace(line.substr(0, tab), c.str());
+    }
+}
+void tune_file_write() {
+    const std::string path = tune_file();
+    if (path.empty()) return;
+    const std::string tmp = path + ".tmp" + std::to_string(static_cast<long long>(getpid()));
+    {
+        std::ofstream out(tmp, std::ios::trunc);
+        for (const auto& kv : g_tune_cache) out << kv.first << '\t' << kv.second << '\n';
+        if (!out) {
+            std::remove(tmp.c_str());
+            return;       // the cache is an optimisation: an unwritable path only loses it
+        }
+    }
+    if (std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
+}
+
+// Time pass-1 ADI launches of candidate configurations on the batch's own
+// buffers (the members' states are not touched) and keep the fastest:
+// coordinate descent over the launch grouping, then work-queue launches,
+// then the 16-row groups (each candidate the best of two runs).
+BatchCfg autotune_cfg(cyl_batch_s* B, const std::vector<BlockRef>& refs, const std::string& key) {
     {
         std::lock_guard<std::mutex> lk(g_tune_mutex);
+        tune_file_read();
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) return it->second;
+        BatchCfg c;
+        if (it != g_tune_cache.end() && BatchCfg::parse(it->second, &c)) return c;
     }
     const int nprob = static_cast<int>(B->heats.size());
     std::vector<AdiPtrs> tp(nprob);
@@ -940,10 +1026,8 @@ int autotune_grouping(cyl_batch_s* B, const std::vector<BlockRef>& refs, const s
     hipEvent_t a, b;
     hip_check(hipEventCreate(&a), "hipEventCreate");
     hip_check(hipEventCreate(&b), "hipEventCreate");
-    int best = 0;
-    float best_ms = 1e30f;
-    for (int grouping = 0; grouping < 3; ++grouping) {
-        const auto ls = build_launches(refs, grouping);
+    auto time_cfg = [&](const BatchCfg& c) {
+        const auto ls = build_launches(refs, c);
         float ms = 1e30f;
         for (int rep = 0; rep < 2; ++rep) {
             hip_check(hipEventRecord(a, B->stream), "hipEventRecord");
@@ -954,12 +1038,24 @@ int autotune_grouping(cyl_batch_s* B, const std::vector<BlockRef>& refs, const s
             hip_check(hipEventElapsedTime(&t, a, b), "hipEventElapsedTime");
             ms = std::min(ms, t);
         }
-        if (ms < best_ms) { best_ms = ms; best = grouping; }
-    }
+        return ms;
+    };
+    BatchCfg best;
+    float best_ms = time_cfg(best);
+    auto consider = [&](BatchCfg c) {
+        const float ms = time_cfg(c);
+        if (ms < best_ms) { best_ms = ms; best = c; }
+    };
+    for (int g = 1; g < 3; ++g) { BatchCfg c = best; c.grouping = g; consider(c); }
+    { BatchCfg c = best; c.queue = true; consider(c); }
+    { BatchCfg c = best; c.g16 = false; consider(c); }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
+    if (env_int("CYLSPEC_LOG", 0) > 0)
+        std::fprintf(stderr, "[cylspec] batch tuned: %s (pass-1 ADI %.3f ms)\n", best.str().c_str(), best_ms);
     std::lock_guard<std::mutex> lk(g_tune_mutex);
-    g_tune_cache[key] = best;
+    g_tune_cache[key] = best.str();
+    tune_file_write();
     return best;
 }
 
@@ -1053,15 +1149,27 @@ void batch_build(cyl_batch_s* B, int flags) {
     upload(B->proj_items, proj_items);
     B->n_res = static_cast<int>(res_items.size());
     B->n_proj = static_cast<int>(proj_items.size());
-    // launch grouping: forced, tuned (cached per batch signature), or one per (kernel, threads)
-    int grouping = env_int("CYLSPEC_BATCH_GROUPING", -1);
-    if (grouping < 0 || grouping > 2)
-        grouping = (flags & CYL_BATCH_NO_TUNE) ? 0 : autotune_grouping(B, refs1, key.str());
+    // launch configuration: tuned (cached per batch signature, in the process
+    // and in CYLSPEC_TUNE_CACHE), or the default; CYLSPEC_BATCH_GROUPING and
+    // CYLSPEC_BATCH_QUEUE fix those parts
+    BatchCfg cfg;
+    const int fg = env_int("CYLSPEC_BATCH_GROUPING", -1), fq = env_int("CYLSPEC_BATCH_QUEUE", -1);
+    if (!(flags & CYL_BATCH_NO_TUNE) && (fg < 0 || fg > 2 || fq < 0)) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+        cfg = autotune_cfg(B, refs1, std::string(prop.gcnArchName) + "/" +
+                                         std::to_string(prop.multiProcessorCount) + "|" + key.str());
+    }
+    if (fg >= 0 && fg <= 2) cfg.grouping = fg;
+    if (fq >= 0) cfg.queue = fq != 0;
     static const char* names[3] = {"per kernel and thread count", "per kernel, thread count and width",
                                    "per kernel"};
-    B->grouping = names[grouping];
-    B->adi1 = build_launches(refs1, grouping);
-    if (!refs2.empty()) B->adi2 = build_launches(refs2, grouping);
+    B->grouping = std::string(names[cfg.grouping]) + (cfg.queue ? ", work-queue launches" : "") +
+                  (cfg.g16 ? "" : ", 8-row groups");
+    B->adi1 = build_launches(refs1, cfg);
+    if (!refs2.empty()) B->adi2 = build_launches(refs2, cfg);
     B->use_graph = (flags & CYL_BATCH_NO_GRAPH) == 0;
     if (B->use_graph) {
         hip_check(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");

@@ -67,6 +67,14 @@ struct AdiPtrs {
     const double* ztab;
     const double* vmu;
 };
+// Work-queue launch of the split kernels (batched launches: the launcher's
+// pointer table is required; no residual is formed): `grid` persistent
+// workgroups take the blocks of the launch in order from `counter` (an int
+// that must be zero when the launch starts; it ends at nblocks + grid).
+struct BlockQueue {
+    int* counter;
+    int grid;
+};
 struct ApplyPtrs {
     const double* E;
     const double* X;
@@ -136,11 +144,16 @@ hipError_t launch_adi(const BlockDesc* blocks, int nblocks, int threads, int np0
 hipError_t launch_adi_split(const BlockDesc* blocks, int nblocks, int threads, int np0,
                             const double* E, double* X, const double* rtab, const double* ztab,
                             const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
-                            const AdiPtrs* pp = nullptr, const ResArgs* res = nullptr, bool g16 = false);
+                            const AdiPtrs* pp = nullptr, const ResArgs* res = nullptr, bool g16 = false,
+                            const BlockQueue* q = nullptr);
 // Every half of the block is a multiple of 16 rows / columns (the split kernel's
 // backward r sweeps and z sweeps may then take groups of 16; g16 of a launch
 // needs it for all its blocks).
 bool adi_split_g16(const BlockDesc& b);
+// Workgroups of a work-queue split launch (np0, threads, LDS bytes; gs: the
+// global-state kernel; g16 its instance) that are resident at once on the
+// device: the grid such a launch should use.
+hipError_t adi_split_queue_grid(int np0, int threads, size_t lds, bool gs, bool g16, int* grid);
 // LDS bytes of the split kernel for padded block sizes mp0 x np0.
 size_t adi_split_lds_bytes(int mp0, int np0);
 // Split sweeps with the block state in global memory (np0 in 136..256, a
@@ -150,7 +163,8 @@ hipError_t launch_adi_split_gs(const BlockDesc* blocks, int nblocks, int threads
                                const double* E, double* X, double* state, int64_t state_stride,
                                const double* rtab, const double* ztab, const double* vmu,
                                bool accumulate, size_t lds_bytes, hipStream_t s,
-                               const AdiPtrs* pp = nullptr, const ResArgs* res = nullptr, bool z16 = false);
+                               const AdiPtrs* pp = nullptr, const ResArgs* res = nullptr, bool z16 = false,
+                               const BlockQueue* q = nullptr);
 // z16: groups of 16 columns in the forward z sweeps; every block must satisfy
 // adi_split_gs_z16 (both z halves multiples of 16).
 bool adi_split_gs_z16(const BlockDesc& b);

@@ -119,3 +119,65 @@ def test_b64_sizes_batch_equals_individual():
     for q, (ha, hb) in enumerate(zip(A, B)):
         a, b = host(ha.read()), host(hb.read())
         assert np.array_equal(a, b), (q, float(np.max(np.abs(a - b))))
+
+
+@pytest.mark.parametrize("grouping", [0, 2])
+def test_work_queue_launches_equal_individual_stepping(grouping, monkeypatch):
+    """Persistent work-queue launches of the split kernels (LDS and global
+    state) take the same blocks through the same code: bit for bit equal to
+    stepping each member alone, over graph replays."""
+    need_gpu()
+    banner("batch work-queue launches grouping=%d" % grouping)
+    monkeypatch.setenv("CYLSPEC_BATCH_QUEUE", "1")
+    monkeypatch.setenv("CYLSPEC_BATCH_GROUPING", str(grouping))
+    probs = _make([SPECS[0], SPECS[2], SPECS[4], SPECS[5], SPECS[6]], S + 600)
+    A = _heats(probs)
+    B = _heats(probs)
+    batch = cyl.Batch(A, tune=False)
+    info = batch.describe()
+    print("  batch:", info, flush=True)
+    assert "work-queue" in info["grouping"]
+    for n in (3, 2):
+        batch.step(n)
+        for h in B:
+            h.step(n)
+        for q, (ha, hb) in enumerate(zip(A, B)):
+            a, b = host(ha.read()), host(hb.read())
+            assert np.array_equal(a, b), (n, q, float(np.max(np.abs(a - b))))
+    batch.close()
+
+
+TUNE_SPECS = [(24, 24, 6, 1, 0.4), (56, 40, 8, 1, 1.1)]
+
+
+def _tune_probe():
+    """Create the batch of TUNE_SPECS (tuned) and print its description."""
+    import json
+    probs = _make(TUNE_SPECS, S + 700)
+    batch = cyl.Batch(_heats(probs))
+    print("PROBE " + json.dumps(batch.describe()), flush=True)
+
+
+def test_tune_cache_file_is_written_and_read(tmp_path):
+    """CYLSPEC_TUNE_CACHE: the first process tunes and writes its choice
+    (one "signature<TAB>configuration" line); a second process finds it and
+    does not tune again (no "batch tuned" line), with the same configuration."""
+    need_gpu()
+    import os
+    import re
+    import subprocess
+    import sys
+    path = tmp_path / "tune.txt"
+    env = dict(os.environ, CYLSPEC_TUNE_CACHE=str(path), CYLSPEC_LOG="1")
+    env.pop("CYLSPEC_BATCH_QUEUE", None)
+    env.pop("CYLSPEC_BATCH_GROUPING", None)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cmd = [sys.executable, "-c", "import tests.test_gpu_batch as t; t._tune_probe()"]
+    runs = [subprocess.run(cmd, cwd=root, env=env, capture_output=True, text=True, timeout=300) for _ in range(2)]
+    for r in runs:
+        assert r.returncode == 0, r.stderr[-2000:]
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and re.fullmatch(r"gfx\S*/\d+\|\S+\tg[012]q[01]s(8|16)", lines[0]), lines
+    assert "batch tuned" in runs[0].stderr and "batch tuned" not in runs[1].stderr
+    desc = [re.search(r"^PROBE (.*)$", r.stdout, re.M).group(1) for r in runs]
+    assert desc[0] == desc[1]
