@@ -35,7 +35,11 @@ Prints one JSON line.  Besides the headline value it carries:
                 the horizontal (disk) Poisson solve Delta_h u = f of
                 Section 4 on the same grid and forcing (transforms plus one
                 banded r-solve per wavenumber and z coefficient), with the
-                solve kernel's algorithmic bandwidth.
+                solve kernel's algorithmic bandwidth;
+  pt_decompose_256
+                the poloidal-toroidal decomposition of Section 4 of a seeded
+                three-component field on the same grid (three forward
+                transforms, two disk solves, two inverse transforms).
 """
 
 import argparse
@@ -96,6 +100,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-physical", action="store_true")
     ap.add_argument("--no-disk", action="store_true")
+    ap.add_argument("--no-pt", action="store_true", help="skip the poloidal-toroidal decomposition leg")
     ap.add_argument("--no-small", action="store_true", help="skip the 32^3 latency leg")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=50)
@@ -441,6 +446,30 @@ def main():
                                    "transforms_ms": (dp["ms_transform_fwd"] + dp["ms_transform_inv"]) / args.steps,
                                    "config": {"workload": "disk_poisson_%d^3_value_space" % m,
                                               "forcing": "seeded decaying random CCF spectrum"}}
+
+    if not args.no_pt:
+        # poloidal-toroidal decomposition of a seeded field (three components)
+        vr, vt = plan.transform_inv(coeff), f
+        vz = plan.transform_inv(torch.from_numpy(synth.smooth_coeffs(m, n, p, synth.SEED_BASE + 6)).cuda())
+        lam, gam = torch.empty_like(f), torch.empty_like(f)
+        plan.pt_decompose(vr, vt, vz, out=(lam, gam))
+        torch.cuda.synchronize()
+        plan.set_profiling(True)
+        plan.profile()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.pt_decompose(vr, vt, vz, out=(lam, gam))
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        pp_ = plan.profile()
+        plan.set_profiling(False)
+        out["pt_decompose_%d" % m] = {
+            "ms_per_call": ms, "unknowns_per_s": m * n * p / (ms * 1e-3),
+            "disk_solves_ms": pp_["ms_adi"] / args.steps,
+            "transforms_ms": (pp_["ms_transform_fwd"] + pp_["ms_transform_inv"]) / args.steps,
+            "config": {"workload": "pt_decomposition_%d^3_value_space" % m,
+                       "field": "three seeded decaying random CCF spectra"}}
+        del vr, vz, lam, gam
 
     if not args.no_small:
         # the smallest configuration (32^3, ADI tolerance 1e-12): bound by the

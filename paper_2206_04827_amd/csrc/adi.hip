@@ -960,6 +960,12 @@ void k_adi_split(const BlockDesc* __restrict__ blocks, const double* __restrict_
 
 // Blocks too large for LDS (n up to 514): split sweeps with the state in
 // global memory, slot blockIdx.x of `state` (state_stride doubles each).
+// Row stride of the global-memory block state: np rounded up to 16 doubles,
+// so that every row starts on a 128-byte cache line (the r-sweeps read and
+// write whole lines of a row, the z-sweeps groups of 16 columns); the LDS
+// kernels pad to np + 1 against bank conflicts instead.
+__host__ __device__ constexpr int gs_row_stride(int np) { return (np + 15) / 16 * 16; }
+
 // kQueue as for k_adi_split; the state slot is the workgroup's.
 template <int NP, int GZF, bool kQueue>
 __global__ __launch_bounds__(512) void k_adi_split_gs(const BlockDesc* __restrict__ blocks,
@@ -978,13 +984,13 @@ __global__ __launch_bounds__(512) void k_adi_split_gs(const BlockDesc* __restric
             const AdiPtrs q = pp[bd.prob];
             E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
         }
-        adi_block_split<NP + 1, true, 8, GZF>(sm, slot, bd, E, X, rtab, ztab, vmu, accumulate, res);
+        adi_block_split<gs_row_stride(NP), true, 8, GZF>(sm, slot, bd, E, X, rtab, ztab, vmu, accumulate, res);
     } else {
         __shared__ int qslot;
         for (int b = queue_next(queue, &qslot); b < nblocks; b = queue_next(queue, &qslot)) {
             const BlockDesc bd = blocks[b];
             const AdiPtrs q = pp[bd.prob];
-            adi_block_split<NP + 1, true, 8, GZF>(sm, slot, bd, q.E, q.X, q.rtab, q.ztab, q.vmu, accumulate,
+            adi_block_split<gs_row_stride(NP), true, 8, GZF>(sm, slot, bd, q.E, q.X, q.rtab, q.ztab, q.vmu, accumulate,
                                                   ResArgs{nullptr, nullptr, nullptr, 0, 0, 0});
         }
     }
@@ -1625,7 +1631,7 @@ size_t adi_split_gs_lds_bytes(int mp0, int np0, int lines, bool residual) {
 }
 
 int64_t adi_split_gs_state_stride(int mp0, int np0) {
-    return static_cast<int64_t>(mp0) * (np0 + 1) + 64;
+    return static_cast<int64_t>(mp0) * gs_row_stride(np0) + 64;
 }
 
 hipError_t launch_adi_split_gs(const BlockDesc* blocks, int nblocks, int threads, int np0,

@@ -8,9 +8,12 @@
 //        imaginary parts at once.
 // Every DFT is a mixed-radix Stockham FFT in LDS whose butterflies run in
 // registers (radices 16, 8, 4, 2 and 3, 5, 7, 11, 13, 15, 17); the twiddle
-// table is staged in LDS once per workgroup.  Lengths with another prime
-// factor go through Bluestein's chirp-z identity with a power-of-two
-// convolution.
+// table is staged in LDS once per workgroup.  One larger prime factor (up to
+// 257) is taken as a direct first pass by all threads of a line together
+// (prime_pass); lengths with other factors go through Bluestein's chirp-z
+// identity with a power-of-two convolution.
+#include <cstdlib>
+
 #include "kernels.hpp"
 
 namespace cyl {
@@ -731,16 +734,31 @@ __global__ __launch_bounds__(512) void k_theta_inv(const double2* __restrict__ p
 // LDS, up to 32 (long contiguous segments per element index: 30 lines of
 // 255 points measured 7-10% faster than 16), contiguous lines fill 256
 // threads.
+int env_knob(const char* name, int def) {
+    const char* v = std::getenv(name);
+    return v ? std::atoi(v) : def;
+}
+
 void line_config(int Nb, int tpl, bool strided, int* TPL, int* LPW, int* threads, size_t* lds) {
+    // lines per workgroup: strided lines (theta, z) take up to kMaxLines lines
+    // within an LDS budget (neighbouring lines are neighbouring in memory: 8
+    // complex lines are one 128-byte cache line, so every load and store of a
+    // workgroup covers whole lines; measured as fast as 32 lines at 256^3 and
+    // 4% faster at 512^3, where 10 lines read each line twice);
+    // contiguous lines (r) fill a workgroup of kThreads threads.  Read once
+    // from the environment for A/B measurements.
+    static const int kMaxLines = env_knob("CYLSPEC_DCT_LINES", 8);
+    static const int kBudget = env_knob("CYLSPEC_DCT_LDS_BUDGET", 150000);
+    static const int kThreads = env_knob("CYLSPEC_DCT_THREADS", 256);
     *TPL = tpl;
     int l;
     if (strided) {
-        l = static_cast<int>(150000 / (static_cast<size_t>(line_stride(Nb)) * sizeof(double2)));
-        if (l > 32) l = 32;
+        l = static_cast<int>(kBudget / (static_cast<size_t>(line_stride(Nb)) * sizeof(double2)));
+        if (l > kMaxLines) l = kMaxLines;
         if (l * *TPL < 64) l = (64 + *TPL - 1) / *TPL;
         if (l * *TPL > 512) l = 512 / *TPL;
     } else {
-        l = *TPL >= 256 ? 1 : 256 / *TPL;
+        l = *TPL >= kThreads ? 1 : kThreads / *TPL;
     }
     // the lines and the twiddle table must fit the CU's 160 KB of LDS
     while (l > 1 && (static_cast<size_t>(l) * line_stride(Nb) + Nb) * sizeof(double2) > 163840) --l;
