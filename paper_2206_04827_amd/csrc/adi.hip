@@ -307,26 +307,50 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Rows of a split kernel's block state, stride LD.  kBand (state in global
+// memory): rows [b0, b0 + nb) are kept in LDS at l instead, so their reads
+// and writes in every sweep stay on the chip.
+template <int LD, bool kBand>
+struct StateRows {
+    double* g;
+    double* l;
+    int b0, nb;
+    __device__ __forceinline__ double* row(int i) const {
+        if constexpr (kBand) {
+            if (static_cast<unsigned>(i - b0) < static_cast<unsigned>(nb)) return l + (i - b0) * LD;
+        }
+        return g + i * LD;
+    }
+    // Element (i0 + q, k) from the group base at(i0, k): plain pointer steps
+    // without a band (the code the sweeps were tuned with), the row lookup
+    // with one.
+    __device__ __forceinline__ double* at(int i0, int k) const { return g + i0 * LD + k; }
+    __device__ __forceinline__ double& el(double* base, int i0, int q, int k) const {
+        if constexpr (kBand) return row(i0 + q)[k];
+        else return base[q * LD];
+    }
+};
+
 // r-pass, rows [0, t) of column k (LU records).  pre: W rows t, t+1, t+2 of
 // this column, read before any thread overwrote them.  Returns g_{t-2}, g_{t-1}.
-template <int LD, int G>
-__device__ __forceinline__ void rs_top_fwd(double* __restrict__ S, int t, int k,
+template <int LD, int G, class ST>
+__device__ __forceinline__ void rs_top_fwd(const ST& S, int t, int k,
                                            const double* __restrict__ RC,
                                            const double* __restrict__ Ecol, double vmu,
                                            const double pre[3], double* gt2, double* gt1) {
     const double2* E2 = reinterpret_cast<const double2*>(Ecol);
     static_assert(G >= 4 && G % 2 == 0, "row group");
-    double* Sk = S + k;
     double wv[G + 6];              // rows i0-2 .. i0+G+3 of W
     wv[0] = 0.0; wv[1] = 0.0;
+    double* Sk = S.at(0, k);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) wv[2 + q] = Sk[q * LD];
+    for (int q = 0; q < 4; ++q) wv[2 + q] = S.el(Sk, 0, q, k);
     double2 eb[G / 2], en[G / 2];
 #pragma unroll
     for (int q = 0; q < G / 2; ++q) { eb[q] = E2[q]; en[q] = E2[G / 2 + q]; }
     double g1 = 0.0, g2 = 0.0;
     for (int i0 = 0; i0 < t; i0 += G) {
-        double* Sg = Sk + i0 * LD;
+        double* Sg = S.at(i0, k);
         const double2* Rg = reinterpret_cast<const double2*>(RC + i0 * kRRec);
         double c[G][8];
 #pragma unroll
@@ -339,10 +363,10 @@ __device__ __forceinline__ void rs_top_fwd(double* __restrict__ S, int t, int k,
             }
         if (i0 + G < t) {
 #pragma unroll
-            for (int q = 0; q < G; ++q) wv[6 + q] = Sg[(4 + q) * LD];
+            for (int q = 0; q < G; ++q) wv[6 + q] = S.el(Sg, i0, 4 + q, k);
         } else {
 #pragma unroll
-            for (int q = 0; q < G - 4; ++q) wv[6 + q] = Sg[(4 + q) * LD];
+            for (int q = 0; q < G - 4; ++q) wv[6 + q] = S.el(Sg, i0, 4 + q, k);
             wv[G + 2] = pre[0]; wv[G + 3] = pre[1]; wv[G + 4] = pre[2]; wv[G + 5] = 0.0;
         }
         double2 enn[G / 2];
@@ -360,7 +384,7 @@ __device__ __forceinline__ void rs_top_fwd(double* __restrict__ S, int t, int k,
         for (int q = 0; q < G; ++q) {
             const double tq = h[q] - c[q][6] * g2;
             const double g = tq - c[q][7] * g1;
-            Sg[q * LD] = g;
+            S.el(Sg, i0, q, k) = g;
             g2 = g1;
             g1 = g;
         }
@@ -374,16 +398,16 @@ __device__ __forceinline__ void rs_top_fwd(double* __restrict__ S, int t, int k,
 }
 
 // r-pass back substitution on rows t-1 .. 0, starting from x_t, x_{t+1}, x_{t+2}.
-template <int LD, int G>
-__device__ __forceinline__ void rs_top_bwd(double* __restrict__ S, int t, int k,
+template <int LD, int G, class ST>
+__device__ __forceinline__ void rs_top_bwd(const ST& S, int t, int k,
                                            const double* __restrict__ RC, double z1, double z2,
                                            double z3) {
-    double* Sk = S + k;
     double gb[G];
+    double* St0 = S.at(t - G, k);
 #pragma unroll
-    for (int q = 0; q < G; ++q) gb[q] = Sk[(t - G + q) * LD];
+    for (int q = 0; q < G; ++q) gb[q] = S.el(St0, t - G, q, k);
     for (int i0 = t - G; i0 >= 0; i0 -= G) {
-        double* Sg = Sk + i0 * LD;
+        double* Sg = S.at(i0, k);
         const double2* Rg = reinterpret_cast<const double2*>(RC + i0 * kRRec + 8);
         double c[G][4];
 #pragma unroll
@@ -397,13 +421,13 @@ __device__ __forceinline__ void rs_top_bwd(double* __restrict__ S, int t, int k,
         double gn[G];
         if (i0 > 0) {
 #pragma unroll
-            for (int q = 0; q < G; ++q) gn[q] = Sg[(q - G) * LD];
+            for (int q = 0; q < G; ++q) gn[q] = S.el(Sg, i0, q - G, k);
         }
 #pragma unroll
         for (int q = G - 1; q >= 0; --q) {
             const double tq = c[q][0] * gb[q] - c[q][3] * z3 - c[q][2] * z2;
             const double z = tq - c[q][1] * z1;
-            Sg[q * LD] = z;
+            S.el(Sg, i0, q, k) = z;
             z3 = z2; z2 = z1; z1 = z;
         }
 #pragma unroll
@@ -413,14 +437,13 @@ __device__ __forceinline__ void rs_top_bwd(double* __restrict__ S, int t, int k,
 
 // r-pass, rows mp-1 .. t of column k (UL records, upwards).  preb: W rows
 // t-2, t-1 of this column.  Returns g'_t, g'_{t+1}, g'_{t+2}.
-template <int LD, int G>
-__device__ __forceinline__ void rs_bot_fwd(double* __restrict__ S, int mp, int t, int k,
+template <int LD, int G, class ST>
+__device__ __forceinline__ void rs_bot_fwd(const ST& S, int mp, int t, int k,
                                            const double* __restrict__ RC,
                                            const double* __restrict__ Ecol, double vmu,
                                            const double preb[2], double* g0, double* g1,
                                            double* g2) {
     const double2* E2 = reinterpret_cast<const double2*>(Ecol);
-    double* Sk = S + k;
     static_assert(G >= 4 && G % 2 == 0, "row group");
     double up[3] = {0.0, 0.0, 0.0};        // old W rows i0+G .. i0+G+2
     double gp1 = 0.0, gp2 = 0.0, gp3 = 0.0;  // g'_{i+1}, g'_{i+2}, g'_{i+3}
@@ -428,7 +451,7 @@ __device__ __forceinline__ void rs_bot_fwd(double* __restrict__ S, int mp, int t
 #pragma unroll
     for (int q = 0; q < G / 2; ++q) { eb[q] = E2[(mp - G) / 2 + q]; en[q] = E2[(mp - 2 * G) / 2 + q]; }
     for (int i0 = mp - G; i0 >= t; i0 -= G) {
-        double* Sg = Sk + i0 * LD;
+        double* Sg = S.at(i0, k);
         const double2* Rg = reinterpret_cast<const double2*>(RC + i0 * kRRec);
         double c[G][10];
 #pragma unroll
@@ -441,14 +464,14 @@ __device__ __forceinline__ void rs_bot_fwd(double* __restrict__ S, int mp, int t
             }
         double w[G + 5];                   // rows i0-2 .. i0+G+2 of W
         if (i0 > t) {
-            w[0] = Sg[-2 * LD];
-            w[1] = Sg[-LD];
+            w[0] = S.el(Sg, i0, -2, k);
+            w[1] = S.el(Sg, i0, -1, k);
         } else {
             w[0] = preb[0];
             w[1] = preb[1];
         }
 #pragma unroll
-        for (int q = 0; q < G; ++q) w[2 + q] = Sg[q * LD];
+        for (int q = 0; q < G; ++q) w[2 + q] = S.el(Sg, i0, q, k);
         w[G + 2] = up[0]; w[G + 3] = up[1]; w[G + 4] = up[2];
         double2 enn[G / 2];
         if (i0 >= 2 * G) {
@@ -470,7 +493,7 @@ __device__ __forceinline__ void rs_bot_fwd(double* __restrict__ S, int mp, int t
         for (int q = G - 1; q >= 0; --q) {
             const double tq = h[q] - c[q][8] * gp3 - c[q][7] * gp2;
             const double g = tq - c[q][6] * gp1;
-            Sg[q * LD] = g;
+            S.el(Sg, i0, q, k) = g;
             gp3 = gp2; gp2 = gp1; gp1 = g;
         }
         up[0] = w[2]; up[1] = w[3]; up[2] = w[4];
@@ -483,15 +506,15 @@ __device__ __forceinline__ void rs_bot_fwd(double* __restrict__ S, int mp, int t
 }
 
 // r-pass forward substitution on rows t .. mp-1, starting from x_{t-1}, x_{t-2}.
-template <int LD, int G>
-__device__ __forceinline__ void rs_bot_bwd(double* __restrict__ S, int mp, int t, int k,
+template <int LD, int G, class ST>
+__device__ __forceinline__ void rs_bot_bwd(const ST& S, int mp, int t, int k,
                                            const double* __restrict__ RC, double xm1, double xm2) {
-    double* Sk = S + k;
     double gb[G];
+    double* St0 = S.at(t, k);
 #pragma unroll
-    for (int q = 0; q < G; ++q) gb[q] = Sk[(t + q) * LD];
+    for (int q = 0; q < G; ++q) gb[q] = S.el(St0, t, q, k);
     for (int i0 = t; i0 < mp; i0 += G) {
-        double* Sg = Sk + i0 * LD;
+        double* Sg = S.at(i0, k);
         const double2* Rg = reinterpret_cast<const double2*>(RC + i0 * kRRec + 8);
         double c[G][3];
 #pragma unroll
@@ -502,13 +525,13 @@ __device__ __forceinline__ void rs_bot_bwd(double* __restrict__ S, int mp, int t
         double gn[G];
         if (i0 + G < mp) {
 #pragma unroll
-            for (int q = 0; q < G; ++q) gn[q] = Sg[(G + q) * LD];
+            for (int q = 0; q < G; ++q) gn[q] = S.el(Sg, i0, G + q, k);
         }
 #pragma unroll
         for (int q = 0; q < G; ++q) {
             const double tq = c[q][0] * gb[q] - c[q][2] * xm2;
             const double x = tq - c[q][1] * xm1;
-            Sg[q * LD] = x;
+            S.el(Sg, i0, q, k) = x;
             xm2 = xm1; xm1 = x;
         }
 #pragma unroll
@@ -693,7 +716,7 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
                                                 const double* __restrict__ rtab,
                                                 const double* __restrict__ ztab,
                                                 const double* __restrict__ vmu, int accumulate,
-                                                const ResArgs& res) {
+                                                const ResArgs& res, int lds_doubles = 0) {
     const int me = bd.me, ne = bd.ne, mp = bd.mp, np = bd.np, tr = bd.tr, tz = bd.tz;
     const int tid = threadIdx.x, nt = blockDim.x, L = nt >> 1;
     const int line = tid % L;
@@ -714,7 +737,21 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
     double* RCs = kGS ? sm : S + mp * LD;
     double* ZCs = RCs + lds_chunks(nr);
     double* XC = ZCs + lds_chunks(nz);
-    for (int idx = tid; idx < mp * LD; idx += nt) S[idx] = 0.0;
+    // kGS: the rows around the r split (read and written in every sweep like
+    // all others) that fit in the LDS left after the records and the exchange
+    // area stay in LDS (lds_doubles: the launch's LDS, in doubles)
+    StateRows<LD, kGS> St{S, nullptr, 0, 0};
+    if constexpr (kGS) {
+        double* band = XC + (5 * L + 15) / 16 * 16;
+        const int room = (lds_doubles - static_cast<int>(band - sm)) / LD;
+        St.nb = room < 0 ? 0 : (room < mp ? room : mp);
+        const int b0 = tr - St.nb / 2;
+        St.b0 = b0 < 0 ? 0 : (b0 > mp - St.nb ? mp - St.nb : b0);
+        St.l = band;
+        for (int idx = tid; idx < mp * LD; idx += nt) St.row(idx / LD)[idx % LD] = 0.0;
+    } else {
+        for (int idx = tid; idx < mp * LD; idx += nt) S[idx] = 0.0;
+    }
     copy_to_lds(RCs, rtab + bd.rbase, nr);
     copy_to_lds(ZCs, ztab + bd.zbase, nz);
     __builtin_amdgcn_s_waitcnt(0);
@@ -727,22 +764,22 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
         if (line < ne) {
             if (top) {
 #pragma unroll
-                for (int s = 0; s < 3; ++s) pre[s] = S[(tr + s) * LD + line];
+                for (int s = 0; s < 3; ++s) pre[s] = St.row(tr + s)[line];
             } else {
 #pragma unroll
-                for (int s = 0; s < 2; ++s) pre[s] = S[(tr - 2 + s) * LD + line];
+                for (int s = 0; s < 2; ++s) pre[s] = St.row(tr - 2 + s)[line];
             }
         }
         half_barrier<kGS>();
         if (line < ne) {
             if (top) {
                 double a, b;
-                rs_top_fwd<LD, GG>(S, tr, line, RCs, Ecol, vm, pre, &a, &b);
+                rs_top_fwd<LD, GG>(St, tr, line, RCs, Ecol, vm, pre, &a, &b);
                 XC[line] = a;
                 XC[L + line] = b;
             } else {
                 double a, b, c;
-                rs_bot_fwd<LD, GG>(S, mp, tr, line, RCs, Ecol, vm, pre, &a, &b, &c);
+                rs_bot_fwd<LD, GG>(St, mp, tr, line, RCs, Ecol, vm, pre, &a, &b, &c);
                 XC[2 * L + line] = a;
                 XC[3 * L + line] = b;
                 XC[4 * L + line] = c;
@@ -758,15 +795,15 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
             for (int r = 0; r < 5; ++r)
                 y[r] = K5[5 * r] * v[0] + K5[5 * r + 1] * v[1] + K5[5 * r + 2] * v[2] +
                        K5[5 * r + 3] * v[3] + K5[5 * r + 4] * v[4];
-            if (top) rs_top_bwd<LD, GB>(S, tr, line, RCs, y[2], y[3], y[4]);
-            else rs_bot_bwd<LD, GB>(S, mp, tr, line, RCs, y[1], y[0]);
+            if (top) rs_top_bwd<LD, GB>(St, tr, line, RCs, y[2], y[3], y[4]);
+            else rs_bot_bwd<LD, GB>(St, mp, tr, line, RCs, y[1], y[0]);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         const bool more = j + 1 < bd.J;
         if (more) copy_to_lds(RCs, rtab + bd.rbase + (j + 1) * bd.rstride, nr);
         // ---- z-pass: lines are rows
-        double* row = S + line * LD;
+        double* row = St.row(line);
         if (line < me) {
             if (top) {
                 XC[line] = zs_top_fwd<GZF>(row, tz, ZCs);
@@ -799,10 +836,16 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
     double* Xb = X + bd.xoff;
     for (int idx = tid; idx < me * ne; idx += nt) {
         const int i = idx / ne, k = idx - i * ne;
-        const double v = S[i * LD + k];
+        const double v = St.row(i)[k];
         Xb[idx] = accumulate ? Xb[idx] + v : v;
     }
     if (res.R != nullptr) {
+        if constexpr (kGS) {
+            // the epilogue reuses the LDS: the band rows go back to their slot rows
+            __syncthreads();
+            for (int idx = tid; idx < St.nb * LD; idx += nt) S[(St.b0 + idx / LD) * LD + idx % LD] = St.l[idx];
+            __syncthreads();
+        }
         // R = E - (A X B + C X D) from the solution still held in S (the
         // block is the whole parity problem: outside it X is zero).  Tiles of
         // 64 rows by TK columns; a lane owns a row, a wave a run of columns
@@ -975,7 +1018,7 @@ __global__ __launch_bounds__(512) void k_adi_split_gs(const BlockDesc* __restric
                                                       const double* __restrict__ ztab,
                                                       const double* __restrict__ vmu, int accumulate,
                                                       const AdiPtrs* __restrict__ pp, ResArgs res, int* queue,
-                                                      int nblocks) {
+                                                      int nblocks, int lds_doubles) {
     extern __shared__ double sm[];
     double* slot = state + static_cast<int64_t>(blockIdx.x) * state_stride;
     if constexpr (!kQueue) {
@@ -984,14 +1027,15 @@ __global__ __launch_bounds__(512) void k_adi_split_gs(const BlockDesc* __restric
             const AdiPtrs q = pp[bd.prob];
             E = q.E; X = q.X; rtab = q.rtab; ztab = q.ztab; vmu = q.vmu;
         }
-        adi_block_split<gs_row_stride(NP), true, 8, GZF>(sm, slot, bd, E, X, rtab, ztab, vmu, accumulate, res);
+        adi_block_split<gs_row_stride(NP), true, 8, GZF>(sm, slot, bd, E, X, rtab, ztab, vmu, accumulate, res,
+                                                         lds_doubles);
     } else {
         __shared__ int qslot;
         for (int b = queue_next(queue, &qslot); b < nblocks; b = queue_next(queue, &qslot)) {
             const BlockDesc bd = blocks[b];
             const AdiPtrs q = pp[bd.prob];
             adi_block_split<gs_row_stride(NP), true, 8, GZF>(sm, slot, bd, q.E, q.X, q.rtab, q.ztab, q.vmu, accumulate,
-                                                  ResArgs{nullptr, nullptr, nullptr, 0, 0, 0});
+                                                             ResArgs{nullptr, nullptr, nullptr, 0, 0, 0}, lds_doubles);
         }
     }
 }
@@ -1523,21 +1567,22 @@ hipError_t launch_split_gs(const BlockDesc* blocks, int nblocks, int threads, co
                            const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
                            const AdiPtrs* pp, const ResArgs& res, bool z16, const BlockQueue* q) {
     const int acc = accumulate ? 1 : 0;
+    const int band = static_cast<int>(lds_bytes / sizeof(double));   // LDS doubles (the band takes the rest)
     if (q != nullptr && (pp == nullptr || q->counter == nullptr)) return hipErrorInvalidValue;
     if (q != nullptr) {
         const dim3 grid(static_cast<unsigned>(std::min(q->grid, nblocks)));
         if (z16)
             hipLaunchKernelGGL((k_adi_split_gs<NP, 16, true>), grid, dim3(threads), lds_bytes, s, blocks, E, X,
-                               state, state_stride, rtab, ztab, vmu, acc, pp, res, q->counter, nblocks);
+                               state, state_stride, rtab, ztab, vmu, acc, pp, res, q->counter, nblocks, band);
         else
             hipLaunchKernelGGL((k_adi_split_gs<NP, 8, true>), grid, dim3(threads), lds_bytes, s, blocks, E, X,
-                               state, state_stride, rtab, ztab, vmu, acc, pp, res, q->counter, nblocks);
+                               state, state_stride, rtab, ztab, vmu, acc, pp, res, q->counter, nblocks, band);
     } else if (z16) {
         hipLaunchKernelGGL((k_adi_split_gs<NP, 16, false>), dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E,
-                           X, state, state_stride, rtab, ztab, vmu, acc, pp, res, nullptr, nblocks);
+                           X, state, state_stride, rtab, ztab, vmu, acc, pp, res, nullptr, nblocks, band);
     } else {
         hipLaunchKernelGGL((k_adi_split_gs<NP, 8, false>), dim3(nblocks), dim3(threads), lds_bytes, s, blocks, E,
-                           X, state, state_stride, rtab, ztab, vmu, acc, pp, res, nullptr, nblocks);
+                           X, state, state_stride, rtab, ztab, vmu, acc, pp, res, nullptr, nblocks, band);
     }
     return hipGetLastError();
 }

@@ -553,6 +553,22 @@ Work plan_work(cyl_plan_s* pl) {
     return w;
 }
 
+// LDS of a global-state split launch: everything a workgroup may use when
+// the LDS band is on (its rows around the r split stay on the chip), else
+// what the records, the exchange area (and the residual epilogue) need.
+size_t gs_launch_lds(size_t needed) {
+    if (env_int("CYLSPEC_ADI_GS_BAND", 1) == 0) return needed;
+    int dev = 0, lim = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return needed;
+    int per_cu = 0;
+    if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess)
+        lim = std::max(lim, per_cu);
+    // 1 KB below the limit: room for the work-queue instances' static LDS
+    return std::max(needed, static_cast<size_t>(lim) - 1024);
+}
+
 // Two passes with split kernels: the first pass writes the residual of its
 // own solution (no separate residual launch).  Every round of resident blocks
 // then ends in a burst of E and R traffic; measured, this pays only with at
@@ -785,7 +801,7 @@ void build_plan(cyl_plan_t pl) {
         pl->split_gs = true;
         pl->adi_threads = 2 * lines;
         pl->fused_res = env_int("CYLSPEC_ADI_FUSED_RES", 1);
-        pl->lds_bytes = adi_split_gs_lds_bytes(g.mp[0], g.np[0], lines, pl->fused_res != 0);
+        pl->lds_bytes = gs_launch_lds(adi_split_gs_lds_bytes(g.mp[0], g.np[0], lines, pl->fused_res != 0));
         if (pl->lds_bytes > 65536 && adi_split_gs_set_lds_limit(g.np[0], pl->lds_bytes) != hipSuccess) {
             (void)hipGetLastError();
             pl->fused_res = 0;
@@ -877,9 +893,10 @@ std::vector<BatchLaunch> build_launches(const std::vector<BlockRef>& refs, const
             l.lds = (static_cast<size_t>(mp + 4) * (l.np + 1) + chunks(kRRec * mp) + chunks(kZRec * l.np)) * sizeof(double);
             if (l.lds > 65536) hip_check(adi_set_lds_limit(l.np, l.lds), "LDS limit");
         } else if (l.kind == 3) {
-            // the kernel's row stride is the group's np + 1: size every slot for
-            // the group's largest mp at that stride
-            l.lds = adi_split_gs_lds_bytes(mp, l.np, l.threads / 2, false);
+            // the kernel's row stride follows the group's np: size every slot
+            // for the group's largest mp at that stride
+            l.lds = gs_launch_lds(adi_split_gs_lds_bytes(mp, l.np, l.threads / 2, false));
+            if (l.lds > 65536) hip_check(adi_split_gs_set_lds_limit(l.np, l.lds), "LDS limit");
             l.state_stride = adi_split_gs_state_stride(mp, l.np);
             l.state = std::make_unique<DevMem>();
             l.state->alloc(static_cast<size_t>(l.nblocks) * l.state_stride * sizeof(double));
