@@ -44,6 +44,26 @@ def test_p32_config_full_field():
     assert info["resid_ratio"] < 1e-9
 
 
+def test_solve_info_phase_times():
+    """cyl_solve_info carries this solve's phase times; with profiling off
+    they leave no records behind (the plan's profile stays empty), with
+    profiling on the profile also holds them."""
+    need_gpu()
+    m, n, p = 40, 36, 12
+    plan = cyl.Plan(m, n, p)
+    f = dev(smooth_values(m, n, p, S + 5))
+    _, info = plan.poisson_solve(f, adi_tol=1e-10, info=True)
+    for k in ("ms_transform", "ms_rhs", "ms_adi", "ms_inverse"):
+        assert info[k] > 0.0, (k, info)
+    prof = plan.profile()
+    assert prof["n_adi"] == 0 and prof["n_transform_fwd"] == 0, prof
+    plan.set_profiling(True)
+    _, info = plan.poisson_solve(f, adi_tol=1e-10, info=True)
+    prof = plan.profile()
+    plan.set_profiling(False)
+    assert prof["n_adi"] >= 1 and abs(prof["ms_adi"] + prof["ms_residual"] - info["ms_adi"]) < 1e-9, (prof, info)
+
+
 @pytest.mark.parametrize("m,n,p", [(6, 5, 3), (20, 17, 9), (33, 41, 12), (64, 48, 20), (47, 80, 1)])
 def test_ragged_sizes_full_field(m, n, p):
     need_gpu()
@@ -187,6 +207,25 @@ def test_adi_16_row_groups_match_8(m, n, p, capfd):
     print("  16-row vs 8-row groups rel max %.3e" % rel)
     assert rel == 0.0
     assert_close(g16, pb.poisson(f), TOL, "16-row groups")
+
+
+@pytest.mark.parametrize("m,n,p,fused", [(290, 270, 3, "2"), (400, 350, 2, "0"), (514, 300, 2, "2")])
+def test_global_state_band_matches_no_band(m, n, p, fused):
+    """The global-state kernel's LDS band changes where rows of the block
+    state live, not the arithmetic: bit-identical solutions with and without
+    it (two passes; with the first pass forming the residual, which writes
+    the band back before its epilogue, and with the separate residual
+    launch), and both match the oracle."""
+    need_gpu()
+    banner("global-state band m=%d n=%d p=%d" % (m, n, p))
+    f = smooth_values(m, n, p, S + 47 + m)
+    env = {"CYLSPEC_PASSES": "2", "CYLSPEC_ADI_FUSED_RES": fused}
+    band = _with_env(env, lambda: _solve_values(m, n, p, f))
+    flat = _with_env(dict(env, CYLSPEC_ADI_GS_BAND="0"), lambda: _solve_values(m, n, p, f))
+    rel = np.max(np.abs(band - flat)) / np.max(np.abs(flat))
+    print("  band vs no band rel max %.3e" % rel)
+    assert rel == 0.0
+    assert_close(band, pb.poisson(f), TOL, "band")
 
 
 @pytest.mark.parametrize("m,n,p,env", [(33, 30, 8, {}), (130, 120, 4, {}),
