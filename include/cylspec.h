@@ -63,7 +63,9 @@ enum { CYL_SPACE_VALUE = 0, CYL_SPACE_COEFF = 1 };
 
 /* Filled by cyl_poisson_solve when a host pointer is given (this synchronises
  * the stream).  resid_ratio = ||E - L(X)||_2 / ||E||_2 over all modes, where
- * L(X) = A X B + C X D is the per-mode operator of eq. (HelmholtzMatEqn). */
+ * L(X) = A X B + C X D is the per-mode operator of eq. (HelmholtzMatEqn).
+ * The ms_ fields are this solve's phases, timed with HIP events on the
+ * plan's stream (the residual check itself is not in them). */
 typedef struct {
     int J_max;          /* most ADI iterations of any mode (per pass)        */
     int J_min;          /* fewest ADI iterations of any mode (per pass)      */
@@ -72,6 +74,10 @@ typedef struct {
                            residual for the second (no separate launch)      */
     double resid_ratio;
     double adi_iterations_mean; /* mean J over real mode planes, per pass   */
+    double ms_transform;  /* forward transforms (value space; 0 otherwise)   */
+    double ms_rhs;        /* tau right side                                  */
+    double ms_adi;        /* ADI passes and the residual between them        */
+    double ms_inverse;    /* recombination and inverse transforms            */
 } cyl_solve_info;
 
 /* Accumulated device time per phase since profiling was enabled (ms), and the

@@ -48,7 +48,8 @@ class CylError(RuntimeError):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("J_max", ctypes.c_int), ("J_min", ctypes.c_int), ("passes", ctypes.c_int),
                 ("fused_residual", ctypes.c_int), ("resid_ratio", ctypes.c_double),
-                ("adi_iterations_mean", ctypes.c_double)]
+                ("adi_iterations_mean", ctypes.c_double), ("ms_transform", ctypes.c_double),
+                ("ms_rhs", ctypes.c_double), ("ms_adi", ctypes.c_double), ("ms_inverse", ctypes.c_double)]
 
 
 _PHASES = ["transform_fwd", "rhs", "adi", "residual", "recombine", "transform_inv", "heat_rhs",

@@ -1199,8 +1199,55 @@ void batch_build(cyl_batch_s* B, int flags) {
 // The Poisson solve of Section 3 (eq. HelmholtzMatEqn without time terms) on
 // workspace w: forward transforms, tau right side, ADI (and the residual
 // correction), optional residual check, recombination, inverse transform.
+// Per-phase times of one solve for cyl_solve_info: the solve's phases are
+// recorded (as when profiling) and read back after the stream has finished;
+// the records stay for cyl_plan_get_profile only if profiling was on.
+struct PhaseTimer {
+    cyl_plan_t pl;
+    cyl_solve_info* info;
+    bool was = false;
+    size_t rec0 = 0;
+    PhaseTimer(cyl_plan_t p, cyl_solve_info* i) : pl(p), info(i) {
+        if (!info) return;
+        was = pl->profiling;
+        rec0 = pl->recs.size();
+        pl->profiling = true;
+    }
+    void finish() {
+        if (!info) return;
+        pl->profiling = was;
+        hip_check(hipStreamSynchronize(pl->stream), "sync");
+        double ms[PH_COUNT] = {0};
+        for (size_t i = rec0; i < pl->recs.size(); ++i) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, pl->recs[i].a, pl->recs[i].b) == hipSuccess) ms[pl->recs[i].phase] += t;
+        }
+        drop();
+        info->ms_transform = ms[PH_FWD];
+        info->ms_rhs = ms[PH_RHS];
+        info->ms_adi = ms[PH_ADI] + ms[PH_RES];
+        info->ms_inverse = ms[PH_REC] + ms[PH_INV];
+        info = nullptr;
+    }
+    void drop() {
+        if (was) return;
+        for (size_t i = rec0; i < pl->recs.size(); ++i) {
+            (void)hipEventDestroy(pl->recs[i].a);
+            (void)hipEventDestroy(pl->recs[i].b);
+        }
+        pl->recs.resize(rec0);
+    }
+    ~PhaseTimer() {           // an error left the solve: restore the flag
+        if (!info) return;
+        pl->profiling = was;
+        (void)hipStreamSynchronize(pl->stream);
+        drop();
+    }
+};
+
 void poisson_run(cyl_plan_t pl, Setup* s, int space, const double* f, const double* bc_lift, double* u,
                  double adi_tol, cyl_solve_info* info, const Work& w) {
+    PhaseTimer timer(pl, info);
     const Geometry& g = pl->geo;
     const double2* F = reinterpret_cast<const double2*>(f);
     const double2* Lc = reinterpret_cast<const double2*>(bc_lift);
@@ -1235,6 +1282,7 @@ void poisson_run(cyl_plan_t pl, Setup* s, int space, const double* f, const doub
                                    g.m, g.n, g.p, pl->stream), "recombine");
     }
     if (space == CYL_SPACE_VALUE) transform_inv(pl, w.planesA, u, w.planesA);
+    timer.finish();
 }
 
 double* ckpt_slot(cyl_heat_grad_s* a, int j) { return a->ckpt.as<double>() + j * a->ck_stride; }
