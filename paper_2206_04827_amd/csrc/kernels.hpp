@@ -21,7 +21,7 @@ struct DftDev {
 
 // Output pairs (X_r, X_{R-r}) one thread computes in the direct pass of a
 // prime radix R > 17 (the first pass of such a plan; see transforms.hip).
-constexpr int kPrimePassOutputs = 6;
+constexpr int kPrimePassOutputs = 9;
 
 // A family of equally strided lines: line = (o, i), o < n_outer, i < n_inner;
 // element e of a line sits at o * outer + i * inner + e * elem (in double2).

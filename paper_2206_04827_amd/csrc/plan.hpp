@@ -83,7 +83,7 @@ constexpr int kMaxRadixPasses = 12;
 // Largest prime radix computed directly (longer prime factors use Bluestein),
 // and the output pairs one thread computes in such a pass.
 constexpr int kMaxPrimeRadix = 257;
-constexpr int kPrimeOutputs = 6;
+constexpr int kPrimeOutputs = 9;
 // Per-length DFT tables (complex length L; FFT length Nb = L when L factors
 // into the supported radices, else the power of two >= 2L - 1 of Bluestein).
 struct DftTables {
