@@ -213,8 +213,8 @@ int cyl_disk_poisson_solve(cyl_plan_t plan, int space, const double* f, double* 
  * slot w = n_theta/2 is taken as zero.  The field need not be solenoidal.
  * space: CYL_SPACE_VALUE (all five arrays [n_theta][n_z][n_r] doubles; the
  * outputs may alias the inputs: all inputs are read first) or
- * CYL_SPACE_COEFF (all five coefficient planes; lambda must not alias v_r or
- * v_theta, gamma not v_z).  lambda and gamma must differ.  Enqueued on the
+ * CYL_SPACE_COEFF (all five coefficient planes; neither output may alias an
+ * input).  lambda and gamma must differ.  Enqueued on the
  * plan's stream; uses the plan's three coefficient-plane buffers and
  * allocates nothing.  Timed as the ADI phase when profiling. */
 int cyl_pt_decompose(cyl_plan_t plan, int space, const double* v_r, const double* v_theta, const double* v_z,

@@ -152,6 +152,7 @@ struct cyl_plan_s {
     int fused_res = 0;             //   emitting the first pass's residual itself (0 never,
                                    //   1 with enough blocks per compute unit, 2 always)
     int num_cus = 0;               // compute units of the device
+    int dct_lines = 0;             // z-direction DCT: lines per workgroup at most (tuned; 0: default)
     int device = 0;                // the device current when the plan was created
     int64_t state_stride = 0;
     int adi_threads = 64;
@@ -486,7 +487,8 @@ void transform_fwd(cyl_plan_t pl, const double* values, double2* coeffs) {
     const Geometry& g = pl->geo;
     hip_check(launch_theta_fwd(values, coeffs, g.m, g.n, g.p, pl->dth.view, pl->stream), "theta_fwd");
     hip_check(launch_dct(coeffs, coeffs, z_lines(g), g.n, false, pl->dz.view, pl->pre_fz.as<double>(),
-                         pl->post_fz.as<double>(), pl->fold_z.as<double2>(), pl->stream), "dct_z_fwd");
+                         pl->post_fz.as<double>(), pl->fold_z.as<double2>(), pl->stream, pl->dct_lines),
+              "dct_z_fwd");
     hip_check(launch_dct(coeffs, coeffs, r_lines(g), g.m, true, pl->dr.view, pl->pre_fr.as<double>(),
                          pl->post_fr.as<double>(), pl->fold_r.as<double2>(), pl->stream), "dct_r_fwd");
 }
@@ -500,7 +502,8 @@ void transform_inv(cyl_plan_t pl, const double2* coeffs, double* values, double2
     hip_check(launch_dct(coeffs, W, r_lines(g), g.m, true, pl->dr.view, pl->pre_ir.as<double>(),
                          pl->post_ir.as<double>(), pl->fold_r.as<double2>(), pl->stream), "dct_r_inv");
     hip_check(launch_dct(W, W, z_lines(g), g.n, false, pl->dz.view, pl->pre_iz.as<double>(),
-                         pl->post_iz.as<double>(), pl->fold_z.as<double2>(), pl->stream), "dct_z_inv");
+                         pl->post_iz.as<double>(), pl->fold_z.as<double2>(), pl->stream, pl->dct_lines),
+              "dct_z_inv");
     hip_check(launch_theta_inv(W, values, g.m, g.n, g.p, pl->dth.view, pl->stream), "theta_inv");
 }
 
@@ -663,6 +666,46 @@ void validate_space(int space) {
     if (space != CYL_SPACE_VALUE && space != CYL_SPACE_COEFF) fail(CYL_E_INVALID_ARG, "space must be CYL_SPACE_VALUE or CYL_SPACE_COEFF");
 }
 
+// Lines per workgroup of the z-direction DCT, chosen by timing: more lines
+// mean fewer, larger workgroups; the best count depends on the length
+// (measured: 32 at 256^3, 16 at 192^3 and 512^3).  Timed on the plan's own
+// coefficient planes (zero-filled) for plans of at least 2^20 complex
+// coefficients; CYLSPEC_DCT_LINES fixes the count instead.
+void tune_dct_lines(cyl_plan_t pl) {
+    const Geometry& g = pl->geo;
+    const int64_t elems = static_cast<int64_t>(g.nw) * g.n * g.m;
+    if (env_int("CYLSPEC_DCT_LINES", 0) > 0 || env_int("CYLSPEC_TUNE_DCT", 1) == 0 || elems < (1 << 20)) return;
+    double2* A = pl->planesA.as<double2>();
+    hip_check(launch_fill_zero(reinterpret_cast<double*>(A), 2 * elems, pl->stream), "zero planes");
+    struct Ev {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Ev() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    hip_check(hipEventCreate(&ev.a), "hipEventCreate");
+    hip_check(hipEventCreate(&ev.b), "hipEventCreate");
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int lines : {8, 16, 32}) {
+        float ms = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            hip_check(hipEventRecord(ev.a, pl->stream), "hipEventRecord");
+            hip_check(launch_dct(A, A, z_lines(g), g.n, false, pl->dz.view, pl->pre_fz.as<double>(),
+                                 pl->post_fz.as<double>(), pl->fold_z.as<double2>(), pl->stream, lines),
+                      "dct tuning");
+            hip_check(hipEventRecord(ev.b, pl->stream), "hipEventRecord");
+            hip_check(hipEventSynchronize(ev.b), "hipEventSynchronize");
+            float t = 0.0f;
+            hip_check(hipEventElapsedTime(&t, ev.a, ev.b), "hipEventElapsedTime");
+            if (rep > 0) ms = std::min(ms, t);      // the first run warms the instance up
+        }
+        if (ms < best_ms) { best_ms = ms; best = lines; }
+    }
+    pl->dct_lines = best;
+}
+
 void build_plan(cyl_plan_t pl) {
     const int m = pl->m, n = pl->n, p = pl->p;
     pl->geo = make_geometry(m, n, p);
@@ -816,13 +859,15 @@ void build_plan(cyl_plan_t pl) {
         pl->adi_threads = std::min(512, pl->adi_threads);
         pl->state.alloc(static_cast<size_t>(4 * g.nplanes) * pl->state_stride * sizeof(double));
     }
+    tune_dct_lines(pl);
     if (env_int("CYLSPEC_LOG", 0) > 0)
         std::fprintf(stderr, "[cylspec] plan %dx%dx%d: blocks me=(%d,%d) ne=(%d,%d), ADI %s, %d threads, "
-                             "LDS %zu of %d bytes, DFT Nb r/z/theta = %d/%d/%d\n",
+                             "LDS %zu of %d bytes, DFT Nb r/z/theta = %d/%d/%d, z-DCT lines per workgroup <= %d\n",
                      m, n, p, g.me[0], g.me[1], g.ne[0], g.ne[1],
                      pl->split_gs ? "split, global state" : pl->adi_split ? "LDS-resident split"
                                                            : pl->use_lds ? "LDS-resident" : "HBM-resident",
-                     pl->adi_threads, pl->lds_bytes, max_lds, pl->dr.t.Nb, pl->dz.t.Nb, pl->dth.t.Nb);
+                     pl->adi_threads, pl->lds_bytes, max_lds, pl->dr.t.Nb, pl->dz.t.Nb, pl->dth.t.Nb,
+                     pl->dct_lines > 0 ? pl->dct_lines : 8);
 }
 
 // One BDF1 step of the handle's pencil: X = S^-1 (Pin + Econst), Pout = C~ X B~.
@@ -1611,8 +1656,10 @@ int cyl_pt_decompose(cyl_plan_t plan, int space, const double* v_r, const double
         if (!plan || !v_r || !v_theta || !v_z || !lambda || !gamma) fail(CYL_E_INVALID_ARG, "NULL argument");
         validate_space(space);
         if (lambda == gamma) fail(CYL_E_INVALID_ARG, "lambda and gamma must be different arrays");
-        if (space == CYL_SPACE_COEFF && (lambda == v_r || lambda == v_theta || gamma == v_z))
-            fail(CYL_E_INVALID_ARG, "in coefficient space lambda must not alias v_r or v_theta, gamma not v_z");
+        if (space == CYL_SPACE_COEFF)
+            for (const double* out : {static_cast<const double*>(lambda), static_cast<const double*>(gamma)})
+                if (out == v_r || out == v_theta || out == v_z)
+                    fail(CYL_E_INVALID_ARG, "in coefficient space lambda and gamma must not alias an input");
         cyl_plan_s* pl = plan;
         const Geometry& g = pl->geo;
         const DiskTables& t = *pl->disk;

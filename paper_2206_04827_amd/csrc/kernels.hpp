@@ -106,9 +106,10 @@ hipError_t launch_theta_inv(const double2* planes, double* values, int m, int n,
 // DCT-I of every line: out_k = post[k] * sum_n pre[n] in_n * w_n cos(pi k n / M)
 // (w_n = 1 at both ends, 2 inside), M = mlen - 1, through a length-M DFT
 // (d built for length M); fold[n] = (cos(pi n / M), sin(pi n / M)), n <= M.
+// max_lines: strided lines per workgroup at most (0: the default, 8).
 hipError_t launch_dct(const double2* in, double2* out, const LineSet& ls, int mlen,
                       bool contiguous_lines, const DftDev& d, const double* pre,
-                      const double* post, const double2* fold, hipStream_t s);
+                      const double* post, const double2* fold, hipStream_t s, int max_lines = 0);
 
 // ---- right-hand side (tau rows) and recombination ----
 struct RhsTables {

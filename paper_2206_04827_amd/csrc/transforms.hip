@@ -739,7 +739,8 @@ int env_knob(const char* name, int def) {
     return v ? std::atoi(v) : def;
 }
 
-void line_config(int Nb, int tpl, bool strided, int* TPL, int* LPW, int* threads, size_t* lds) {
+void line_config(int Nb, int tpl, bool strided, int* TPL, int* LPW, int* threads, size_t* lds,
+                 bool theta = false, int max_lines = 0) {
     // lines per workgroup: strided lines (theta, z) take up to kMaxLines lines
     // within an LDS budget (neighbouring lines are neighbouring in memory: 8
     // complex lines are one 128-byte cache line, so every load and store of a
@@ -747,7 +748,9 @@ void line_config(int Nb, int tpl, bool strided, int* TPL, int* LPW, int* threads
     // 4% faster at 512^3, where 10 lines read each line twice);
     // contiguous lines (r) fill a workgroup of kThreads threads.  Read once
     // from the environment for A/B measurements.
-    static const int kMaxLines = env_knob("CYLSPEC_DCT_LINES", 8);
+    static const int kMaxLinesZ = env_knob("CYLSPEC_DCT_LINES", 8);
+    static const int kMaxLinesTheta = env_knob("CYLSPEC_THETA_LINES", 8);
+    const int kMaxLines = theta ? kMaxLinesTheta : (max_lines > 0 ? max_lines : kMaxLinesZ);
     static const int kBudget = env_knob("CYLSPEC_DCT_LDS_BUDGET", 150000);
     static const int kThreads = env_knob("CYLSPEC_DCT_THREADS", 256);
     *TPL = tpl;
@@ -790,7 +793,7 @@ hipError_t launch_theta_fwd(const double* values, double2* planes, int m, int n,
                             const DftDev& d, hipStream_t s) {
     int TPL, LPW, threads;
     size_t lds;
-    line_config(d.Nb, d.tpl, true, &TPL, &LPW, &threads, &lds);
+    line_config(d.Nb, d.tpl, true, &TPL, &LPW, &threads, &lds, true);
     const int64_t lines = static_cast<int64_t>(n) * ((m + 1) / 2);
     const unsigned grid = static_cast<unsigned>((lines + LPW - 1) / LPW);
     if (mixed_plan(d)) {
@@ -807,7 +810,7 @@ hipError_t launch_theta_inv(const double2* planes, double* values, int m, int n,
                             const DftDev& d, hipStream_t s) {
     int TPL, LPW, threads;
     size_t lds;
-    line_config(d.Nb, d.tpl, true, &TPL, &LPW, &threads, &lds);
+    line_config(d.Nb, d.tpl, true, &TPL, &LPW, &threads, &lds, true);
     const int64_t lines = static_cast<int64_t>(n) * ((m + 1) / 2);
     const unsigned grid = static_cast<unsigned>((lines + LPW - 1) / LPW);
     if (mixed_plan(d)) {
@@ -822,10 +825,10 @@ hipError_t launch_theta_inv(const double2* planes, double* values, int m, int n,
 
 hipError_t launch_dct(const double2* in, double2* out, const LineSet& ls, int mlen,
                       bool contiguous_lines, const DftDev& d, const double* pre,
-                      const double* post, const double2* fold, hipStream_t s) {
+                      const double* post, const double2* fold, hipStream_t s, int max_lines) {
     int TPL, LPW, threads;
     size_t lds;
-    line_config(d.Nb, d.tpl, !contiguous_lines, &TPL, &LPW, &threads, &lds);
+    line_config(d.Nb, d.tpl, !contiguous_lines, &TPL, &LPW, &threads, &lds, false, max_lines);
     const int64_t lines = static_cast<int64_t>(ls.n_outer) * ls.n_inner;
     const unsigned grid = static_cast<unsigned>((lines + LPW - 1) / LPW);
 #define CYL_DCT(F, X)                                                                                 \

@@ -88,6 +88,8 @@ def test_pt_rejects_bad_aliasing():
         plan.pt_decompose(h[0], h[1], h[2], out=(h[1], torch.empty_like(h[2])))
     with pytest.raises(cyl.CylError):
         plan.pt_decompose(h[0], h[1], h[2], out=(torch.empty_like(h[0]), h[2]))
+    with pytest.raises(cyl.CylError):
+        plan.pt_decompose(h[0], h[1], h[2], out=(torch.empty_like(h[0]), h[0]))
     same = torch.empty_like(h[0])
     with pytest.raises(cyl.CylError):
         plan.pt_decompose(h[0], h[1], h[2], out=(same, same))
