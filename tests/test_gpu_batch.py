@@ -160,7 +160,8 @@ def _tune_probe():
 
 def test_tune_cache_file_is_written_and_read(tmp_path):
     """CYLSPEC_TUNE_CACHE: the first process tunes and writes its choice
-    (one "signature<TAB>configuration" line); a second process finds it and
+    (one "signature<TAB>configuration" line, beside the entries already in
+    the file; malformed lines are dropped); a second process finds it and
     does not tune again (no "batch tuned" line), with the same configuration."""
     need_gpu()
     import os
@@ -168,6 +169,8 @@ def test_tune_cache_file_is_written_and_read(tmp_path):
     import subprocess
     import sys
     path = tmp_path / "tune.txt"
+    # a foreign entry survives, malformed lines are dropped
+    path.write_text("gfx-other/1|0:8:8:4:1;\tg2q0s8\nnot a line\nkey\tg9q9s9\n")
     env = dict(os.environ, CYLSPEC_TUNE_CACHE=str(path), CYLSPEC_LOG="1")
     env.pop("CYLSPEC_BATCH_QUEUE", None)
     env.pop("CYLSPEC_BATCH_GROUPING", None)
@@ -177,7 +180,10 @@ def test_tune_cache_file_is_written_and_read(tmp_path):
     for r in runs:
         assert r.returncode == 0, r.stderr[-2000:]
     lines = path.read_text().splitlines()
-    assert len(lines) == 1 and re.fullmatch(r"gfx\S*/\d+\|\S+\tg[012]q[01]s(8|16)", lines[0]), lines
+    assert "gfx-other/1|0:8:8:4:1;\tg2q0s8" in lines, lines
+    ours = [l for l in lines if not l.startswith("gfx-other/")]
+    assert len(lines) == 2 and len(ours) == 1, lines
+    assert re.fullmatch(r"gfx\S*/\d+\|\S+\tg[012]q[01]s(8|16)", ours[0]), lines
     assert "batch tuned" in runs[0].stderr and "batch tuned" not in runs[1].stderr
     desc = [re.search(r"^PROBE (.*)$", r.stdout, re.M).group(1) for r in runs]
     assert desc[0] == desc[1]
