@@ -24,6 +24,7 @@
 //             eoff + k * mp + i; rows me..mp-1 are zero.
 //   X-layout  (solutions):                  row-major, element (i, k) at
 //             xoff + i * ne + k.
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -732,6 +733,15 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
     // z sweeps (three values per column): 16 with the state in global memory
     // when every z half is a multiple of 16.
     static_assert(GB % GG == 0 && GZF % GB == 0, "groups of the backward and z sweeps");
+    // accumulate bit 1 (a test switch): fill the LDS this block uses with NaN
+    // first, so that any read of LDS the block has not written shows up as a
+    // non-finite solution
+    if (accumulate & 2) {
+        const int used = kGS ? lds_doubles
+                             : mp * LD + lds_chunks((mp + kRCouple) * kRRec) + lds_chunks((np + kZCouple) * kZRec) + 5 * L;
+        for (int idx = tid; idx < used; idx += nt) sm[idx] = __builtin_nan("");
+        __syncthreads();
+    }
     double* S = kGS ? gS : sm;
     const int nr = (mp + kRCouple) * kRRec, nz = (np + kZCouple) * kZRec;
     double* RCs = kGS ? sm : S + mp * LD;
@@ -837,7 +847,7 @@ __device__ __forceinline__ void adi_block_split(double* sm, double* gS, const Bl
     for (int idx = tid; idx < me * ne; idx += nt) {
         const int i = idx / ne, k = idx - i * ne;
         const double v = St.row(i)[k];
-        Xb[idx] = accumulate ? Xb[idx] + v : v;
+        Xb[idx] = (accumulate & 1) ? Xb[idx] + v : v;
     }
     if (res.R != nullptr) {
         if constexpr (kGS) {
@@ -1536,12 +1546,19 @@ hipError_t set_limit(size_t bytes) {
     return raise_lds_limit(reinterpret_cast<const void*>(&k_adi_lds<NP>), bytes);
 }
 
+// CYLSPEC_ADI_POISON=1 (tests): the split kernels poison their LDS first
+// (bit 1 of their accumulate argument).
+int lds_poison() {
+    const char* v = std::getenv("CYLSPEC_ADI_POISON");
+    return (v && *v && *v != '0') ? 2 : 0;
+}
+
 template <int NP>
 hipError_t launch_split(const BlockDesc* blocks, int nblocks, int threads, const double* E,
                         double* X, const double* rtab, const double* ztab, const double* vmu,
                         bool accumulate, size_t lds_bytes, hipStream_t s, const AdiPtrs* pp,
                         const ResArgs& res, bool g16, const BlockQueue* q) {
-    const int acc = accumulate ? 1 : 0;
+    const int acc = (accumulate ? 1 : 0) | lds_poison();
     if (q != nullptr && (pp == nullptr || q->counter == nullptr)) return hipErrorInvalidValue;
     if (q != nullptr) {
         const dim3 grid(static_cast<unsigned>(std::min(q->grid, nblocks)));
@@ -1566,7 +1583,7 @@ hipError_t launch_split_gs(const BlockDesc* blocks, int nblocks, int threads, co
                            double* state, int64_t state_stride, const double* rtab, const double* ztab,
                            const double* vmu, bool accumulate, size_t lds_bytes, hipStream_t s,
                            const AdiPtrs* pp, const ResArgs& res, bool z16, const BlockQueue* q) {
-    const int acc = accumulate ? 1 : 0;
+    const int acc = (accumulate ? 1 : 0) | lds_poison();
     const int band = static_cast<int>(lds_bytes / sizeof(double));   // LDS doubles (the band takes the rest)
     if (q != nullptr && (pp == nullptr || q->counter == nullptr)) return hipErrorInvalidValue;
     if (q != nullptr) {

@@ -209,6 +209,23 @@ def test_adi_16_row_groups_match_8(m, n, p, capfd):
     assert_close(g16, pb.poisson(f), TOL, "16-row groups")
 
 
+@pytest.mark.parametrize("m,n,p,fused", [(40, 36, 6, "0"), (130, 120, 4, "2"), (256, 256, 2, "2"),
+                                         (290, 270, 3, "2")])
+def test_lds_poisoned_first_gives_the_same_solution(m, n, p, fused):
+    """The split kernels read no LDS they have not written: with their LDS
+    filled with NaN before the block starts (CYLSPEC_ADI_POISON) the solutions
+    are finite and bit-identical to the normal ones (LDS-resident kernel with
+    and without the fused residual, global-state kernel with its band)."""
+    need_gpu()
+    banner("lds poison m=%d n=%d p=%d" % (m, n, p))
+    f = smooth_values(m, n, p, S + 49 + m)
+    env = {"CYLSPEC_PASSES": "2", "CYLSPEC_ADI_FUSED_RES": fused}
+    plain = _with_env(env, lambda: _solve_values(m, n, p, f))
+    poisoned = _with_env(dict(env, CYLSPEC_ADI_POISON="1"), lambda: _solve_values(m, n, p, f))
+    assert np.all(np.isfinite(poisoned))
+    assert np.array_equal(poisoned, plain)
+
+
 @pytest.mark.parametrize("m,n,p,fused", [(290, 270, 3, "2"), (400, 350, 2, "0"), (514, 300, 2, "2")])
 def test_global_state_band_matches_no_band(m, n, p, fused):
     """The global-state kernel's LDS band changes where rows of the block
