@@ -485,17 +485,29 @@ __device__ __forceinline__ void line_thread(int LPW, int TPL, int* li, int* t) {
 // outputs are a prefix sum: each thread scans a contiguous chunk, chunk
 // totals meet in LDS.  out_k = post_k * 2 F_k.
 // LDS: [twiddles: Nb][line 0: line_stride(Nb)][line 1] ...
+// Workgroup b of G runs on XCD b mod 8 (round robin).  With xcd set, it takes
+// line group (b mod 8) G/8 + min(b mod 8, G mod 8) + b / 8 instead of b (a
+// permutation of 0..G-1): neighbouring groups then run on one XCD at about
+// the same time, and cache lines that two groups share (strided lines whose
+// group is not a whole number of 128-byte lines) are fetched into one L2.
+__device__ __forceinline__ int64_t line_group(int xcd) {
+    const unsigned b = blockIdx.x, G = gridDim.x;
+    if (!xcd) return b;
+    const unsigned x = b & 7u, rem = G & 7u;
+    return static_cast<int64_t>(x) * (G >> 3) + (x < rem ? x : rem) + (b >> 3);
+}
+
 template <bool kLineFast, bool kMixed>
 __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, LineSet ls,
                                               int mlen, DftDev d,
                                               const double* __restrict__ pre,
                                               const double* __restrict__ post,
-                                              const double2* __restrict__ fold, int TPL, int LPW) {
+                                              const double2* __restrict__ fold, int TPL, int LPW, int xcd) {
     extern __shared__ double2 lds[];
     double2* tws = lds;
     int li, t;
     line_thread<kLineFast>(LPW, TPL, &li, &t);
-    const int64_t line = static_cast<int64_t>(blockIdx.x) * LPW + li;
+    const int64_t line = line_group(xcd) * LPW + li;
     const int64_t nlines = static_cast<int64_t>(ls.n_outer) * ls.n_inner;
     const bool valid = line < nlines;
     int64_t base = 0;
@@ -831,11 +843,14 @@ hipError_t launch_dct(const double2* in, double2* out, const LineSet& ls, int ml
     line_config(d.Nb, d.tpl, !contiguous_lines, &TPL, &LPW, &threads, &lds, false, max_lines);
     const int64_t lines = static_cast<int64_t>(ls.n_outer) * ls.n_inner;
     const unsigned grid = static_cast<unsigned>((lines + LPW - 1) / LPW);
+    // strided line groups that split 128-byte lines: XCD-aware group order
+    static const int kXcd = env_knob("CYLSPEC_DCT_XCD", 1);
+    const int xcd = (kXcd != 0 && !contiguous_lines && (LPW * 16) % 128 != 0) ? 1 : 0;
 #define CYL_DCT(F, X)                                                                                 \
     do {                                                                                              \
         raise_lds(k_dct<F, X>, lds);                                                                  \
         hipLaunchKernelGGL((k_dct<F, X>), dim3(grid), dim3(threads), lds, s, in, out, ls, mlen, d, pre, post, \
-                           fold, TPL, LPW);                                                           \
+                           fold, TPL, LPW, xcd);                                                      \
     } while (0)
     const bool mixed = mixed_plan(d);
     if (contiguous_lines) {
