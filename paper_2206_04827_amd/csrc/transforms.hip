@@ -741,11 +741,8 @@ __global__ __launch_bounds__(512) void k_theta_inv(const double2* __restrict__ p
     }
 }
 
-// Threads per line: chosen with the radix plan (about Nb / 16).  Lines
-// per workgroup: strided lines take as many lines as keep ~150 KB of data in
-// LDS, up to 32 (long contiguous segments per element index: 30 lines of
-// 255 points measured 7-10% faster than 16), contiguous lines fill 256
-// threads.
+// Threads per line: chosen with the radix plan (about Nb / 16).  Lines per
+// workgroup: line_config below.
 int env_knob(const char* name, int def) {
     const char* v = std::getenv(name);
     return v ? std::atoi(v) : def;
