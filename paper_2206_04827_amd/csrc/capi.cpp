@@ -100,10 +100,10 @@ struct DftOwned {
     DevMem tw, chirp, bhat;
     DftDev view{};
     void build(int L) {
-        t = build_dft_tables(L, env_int("CYLSPEC_DFT_MIXED", 1) != 0);
+        t = build_dft_tables(L, env_int("CYLSPEC_DFT_MIXED", 1) != 0, env_int("CYLSPEC_DFT_POINTS", 8) == 16 ? 16 : 8);
         upload(tw, t.tw);
         if (t.bluestein) { upload(chirp, t.chirp); upload(bhat, t.bhat); }
-        view.L = t.L; view.Nb = t.Nb; view.tpl = t.tpl; view.bluestein = t.bluestein ? 1 : 0;
+        view.L = t.L; view.Nb = t.Nb; view.tpl = t.tpl; view.pts = t.pts; view.bluestein = t.bluestein ? 1 : 0;
         view.nrad = static_cast<int>(t.radices.size());
         for (int i = 0; i < kMaxDftPasses; ++i) view.rad[i] = i < view.nrad ? t.radices[i] : 0;
         view.tw = tw.as<double2>();

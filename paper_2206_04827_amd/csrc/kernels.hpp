@@ -12,6 +12,7 @@ namespace cyl {
 constexpr int kMaxDftPasses = 12;
 struct DftDev {
     int L, Nb, tpl, bluestein;     // tpl: threads per line
+    int pts;                       // points per thread (8 or 16; 16 with a prime pass)
     int nrad;
     int rad[kMaxDftPasses];
     const double2* tw;      // Nb: per-pass twiddles of the Stockham FFT

@@ -776,8 +776,8 @@ bool dft_radix_plan(int N, std::vector<int>* radices) {
     return static_cast<int>(radices->size()) <= kMaxRadixPasses;
 }
 
-int dft_threads_per_line(int N, const std::vector<int>& radices) {
-    int lo = std::max(1, (N + 15) / 16);
+int dft_threads_per_line(int N, const std::vector<int>& radices, int pts) {
+    int lo = std::max(1, (N + pts - 1) / pts);
     for (int R : radices) {
         if (R > 17) {                               // prime pass: one work item per thread
             const int ng = (R / 2 + kPrimeOutputs - 1) / kPrimeOutputs;
@@ -797,7 +797,7 @@ int dft_threads_per_line(int N, const std::vector<int>& radices) {
     return best;
 }
 
-DftTables build_dft_tables(int L, bool mixed) {
+DftTables build_dft_tables(int L, bool mixed, int pts) {
     DftTables t;
     t.L = L;
     const long double pi = 3.141592653589793238462643383279502884L;
@@ -809,7 +809,12 @@ DftTables build_dft_tables(int L, bool mixed) {
     else while (Nb < 2 * L - 1) Nb <<= 1;
     t.Nb = Nb;
     if (!dft_radix_plan(Nb, &t.radices)) throw std::runtime_error("DFT radix plan");
-    t.tpl = dft_threads_per_line(Nb, t.radices);
+    // 8 points per thread (twice the threads of 16, a third fewer registers
+    // with the prime pass in its own instance) for direct FFTs up to 256
+    // points without a prime pass; longer lines and Bluestein measured as fast
+    // or faster with 16
+    t.pts = (pts == 8 && !t.bluestein && Nb <= 256 && !(t.radices.size() > 0 && t.radices[0] > 17)) ? 8 : 16;
+    t.tpl = dft_threads_per_line(Nb, t.radices, t.pts);
     // Per-pass twiddles of the Stockham FFT, in pass order: for the pass of
     // radix R on sub-transforms of length Ls, entries
     // [k (R-1) + q - 1] = exp(-2 pi i k q / (R Ls)), k < Ls, 1 <= q < R

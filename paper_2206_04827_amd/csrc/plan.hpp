@@ -88,21 +88,24 @@ constexpr int kPrimeOutputs = 9;
 // into the supported radices, else the power of two >= 2L - 1 of Bluestein).
 struct DftTables {
     int L = 0, Nb = 0, tpl = 1;     // tpl: threads per line in the kernels
+    int pts = 16;                   // points per thread in the kernels (8 or 16)
     bool bluestein = false;
     std::vector<int> radices;   // Stockham pass radices, first pass first
     std::vector<double> tw;     // 2*Nb: per-pass FFT twiddles (see build_dft_tables)
     std::vector<double> chirp;  // 2*L : exp(-i pi n^2 / L)
     std::vector<double> bhat;   // 2*Nb: FFT of the Bluestein filter, times 1/Nb
 };
-DftTables build_dft_tables(int L, bool mixed = true);
+// pts: points per thread of the kernels, 8 or 16; 8 applies only to direct
+// FFTs of at most 256 points not led by a prime pass (first radix above 17).
+DftTables build_dft_tables(int L, bool mixed = true, int pts = 8);
 // Radix plan of a length-N FFT: a prime factor 19..257 first (at most one,
 // computed directly), an odd prime factor 7, 11, 13 or 17 first (at most one;
 // only 7 after a prime pass), 16/8/4/2 for the power-of-two part, then 15, 5,
 // 3; false for any other N.
 bool dft_radix_plan(int N, std::vector<int>* radices);
-// Threads per line for a length-N FFT with the given passes: at least N / 16
+// Threads per line for a length-N FFT with the given passes: at least N / pts
 // (and N / R for radices R >= 11), balancing the butterflies of every pass.
-int dft_threads_per_line(int N, const std::vector<int>& radices);
+int dft_threads_per_line(int N, const std::vector<int>& radices, int pts = 16);
 
 // Record layouts of the ADI coefficient tables (doubles per row).
 constexpr int kRRec = 12;   // r-pass: (vC - A) row[6], L[2], dinv, dinv*U[3]

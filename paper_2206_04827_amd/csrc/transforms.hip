@@ -12,6 +12,7 @@
 // 257) is taken as a direct first pass by all threads of a line together
 // (prime_pass); lengths with other factors go through Bluestein's chirp-z
 // identity with a power-of-two convolution.
+#include <type_traits>
 #include <cstdlib>
 
 #include "kernels.hpp"
@@ -219,13 +220,13 @@ __device__ __forceinline__ int P(int i) { return i + (i >> 4); }
 // One Stockham pass of radix R over a line of N points in LDS, already
 // combined into sub-transforms of length Ls: butterfly b reads x[b + q N/R],
 // scales input q by exp(-2 pi i k q / (R Ls)) (k = b mod Ls), and writes
-// output r to (b - k) R + k + r Ls.  With T >= N / 16 threads per line a
-// thread runs at most ceil(16 / R) butterflies, and one for R >= 11 (the
+// output r to (b - k) R + k + r Ls.  With T >= N / kP threads per line a
+// thread runs at most ceil(kP / R) butterflies, and one for R >= 11 (the
 // thread count is then at least N / R).  The pass's twiddles are stored as
 // tw[k (R-1) + q - 1].
-template <int R, bool kFirst = false>
+template <int R, bool kFirst, int kP>
 __device__ __forceinline__ void fft_pass(double2* buf, int N, int Ls, const double2* tw, int t, int T) {
-    constexpr int B = R >= 11 ? 1 : (16 + R - 1) / R;
+    constexpr int B = R >= 11 ? 1 : (kP + R - 1) / R;
     const int nb = N / R;
     const bool ls_pow2 = (Ls & (Ls - 1)) == 0;
     double2 x[B][R];
@@ -352,11 +353,12 @@ __device__ __forceinline__ void prime_pass(double2* buf, int N, int R, const dou
 // In-place forward FFT of the line of d.Nb points in LDS (all threads of the
 // workgroup must call it: it contains barriers), one pass per entry of
 // d.rad.  tw: the per-pass twiddle tables, concatenated in pass order
-// (Nb - 1 entries).  kMixed: the radix plan of a directly transformed
-// length, whose odd prime factor 7, 11, 13 or 17 (at most one) comes first,
-// where no twiddles apply; otherwise powers of two only.  Keeping each
+// (Nb - 1 entries).  kMode 0: powers of two only; 1: the radix plan of a
+// directly transformed length, whose odd prime factor 7, 11, 13 or 17 (at
+// most one) comes first, where no twiddles apply; 2: the same led by a prime
+// pass (radix 19..257).  kP: points per thread (T >= Nb / kP).  Keeping each
 // instance to the passes it needs keeps the kernels within their registers.
-template <bool kMixed>
+template <int kMode, int kP>
 __device__ __forceinline__ void fft_lds(double2* buf, const DftDev& d, const double2* tw, int t, int T) {
     const int N = d.Nb;
     int Ls = 1;
@@ -365,39 +367,39 @@ __device__ __forceinline__ void fft_lds(double2* buf, const DftDev& d, const dou
         // opaque per pass: keeps the per-radix LDS addresses from being
         // hoisted out of this loop (and spilled across it)
         asm volatile("" : "+v"(t));
-        if (kMixed && p == 0 && R > 17) {
+        if (kMode == 2 && p == 0 && R > 17) {
             prime_pass(buf, N, R, tw, t, T);
-        } else if (kMixed && p == 0) {
+        } else if (kMode != 0 && p == 0) {
             switch (R) {
-                case 16: fft_pass<16, true>(buf, N, Ls, tw, t, T); break;
-                case 8: fft_pass<8, true>(buf, N, Ls, tw, t, T); break;
-                case 4: fft_pass<4, true>(buf, N, Ls, tw, t, T); break;
-                case 2: fft_pass<2, true>(buf, N, Ls, tw, t, T); break;
-                case 3: fft_pass<3, true>(buf, N, Ls, tw, t, T); break;
-                case 5: fft_pass<5, true>(buf, N, Ls, tw, t, T); break;
-                case 7: fft_pass<7, true>(buf, N, Ls, tw, t, T); break;
-                case 11: fft_pass<11, true>(buf, N, Ls, tw, t, T); break;
-                case 13: fft_pass<13, true>(buf, N, Ls, tw, t, T); break;
-                case 15: fft_pass<15, true>(buf, N, Ls, tw, t, T); break;
-                default: fft_pass<17, true>(buf, N, Ls, tw, t, T); break;
+                case 16: fft_pass<16, true, kP>(buf, N, Ls, tw, t, T); break;
+                case 8: fft_pass<8, true, kP>(buf, N, Ls, tw, t, T); break;
+                case 4: fft_pass<4, true, kP>(buf, N, Ls, tw, t, T); break;
+                case 2: fft_pass<2, true, kP>(buf, N, Ls, tw, t, T); break;
+                case 3: fft_pass<3, true, kP>(buf, N, Ls, tw, t, T); break;
+                case 5: fft_pass<5, true, kP>(buf, N, Ls, tw, t, T); break;
+                case 7: fft_pass<7, true, kP>(buf, N, Ls, tw, t, T); break;
+                case 11: fft_pass<11, true, kP>(buf, N, Ls, tw, t, T); break;
+                case 13: fft_pass<13, true, kP>(buf, N, Ls, tw, t, T); break;
+                case 15: fft_pass<15, true, kP>(buf, N, Ls, tw, t, T); break;
+                default: fft_pass<17, true, kP>(buf, N, Ls, tw, t, T); break;
             }
-        } else if (kMixed) {
+        } else if (kMode != 0) {
             switch (R) {
-                case 16: fft_pass<16>(buf, N, Ls, tw, t, T); break;
-                case 8: fft_pass<8>(buf, N, Ls, tw, t, T); break;
-                case 4: fft_pass<4>(buf, N, Ls, tw, t, T); break;
-                case 2: fft_pass<2>(buf, N, Ls, tw, t, T); break;
-                case 3: fft_pass<3>(buf, N, Ls, tw, t, T); break;
-                case 5: fft_pass<5>(buf, N, Ls, tw, t, T); break;
-                case 7: fft_pass<7>(buf, N, Ls, tw, t, T); break;
-                default: fft_pass<15>(buf, N, Ls, tw, t, T); break;
+                case 16: fft_pass<16, false, kP>(buf, N, Ls, tw, t, T); break;
+                case 8: fft_pass<8, false, kP>(buf, N, Ls, tw, t, T); break;
+                case 4: fft_pass<4, false, kP>(buf, N, Ls, tw, t, T); break;
+                case 2: fft_pass<2, false, kP>(buf, N, Ls, tw, t, T); break;
+                case 3: fft_pass<3, false, kP>(buf, N, Ls, tw, t, T); break;
+                case 5: fft_pass<5, false, kP>(buf, N, Ls, tw, t, T); break;
+                case 7: fft_pass<7, false, kP>(buf, N, Ls, tw, t, T); break;
+                default: fft_pass<15, false, kP>(buf, N, Ls, tw, t, T); break;
             }
         } else {
             switch (R) {
-                case 16: fft_pass<16>(buf, N, Ls, tw, t, T); break;
-                case 8: fft_pass<8>(buf, N, Ls, tw, t, T); break;
-                case 4: fft_pass<4>(buf, N, Ls, tw, t, T); break;
-                default: fft_pass<2>(buf, N, Ls, tw, t, T); break;
+                case 16: fft_pass<16, false, kP>(buf, N, Ls, tw, t, T); break;
+                case 8: fft_pass<8, false, kP>(buf, N, Ls, tw, t, T); break;
+                case 4: fft_pass<4, false, kP>(buf, N, Ls, tw, t, T); break;
+                default: fft_pass<2, false, kP>(buf, N, Ls, tw, t, T); break;
             }
         }
         tw += Ls * (R - 1);
@@ -407,35 +409,34 @@ __device__ __forceinline__ void fft_lds(double2* buf, const DftDev& d, const dou
 
 // DFT of the length-L line held (pre-multiplied by the chirp when Bluestein)
 // in buf[0..Nb); leaves X_k, k < L, in buf[0..L).
-// Every thread owns at most kPts = 16 points of a line (T >= Nb / 16 threads
-// per line), so the pointwise loops below have a fixed trip count and issue
-// all of their table loads before the first use.
-constexpr int kPts = 16;
-
-template <bool kMixed>
+// Every thread owns at most kP (8 or 16, the plan's points per thread)
+// points of a line (T >= Nb / kP threads per line), so the pointwise loops
+// below have a fixed trip count and issue all of their table loads before
+// the first use.
+template <int kMode, int kP>
 __device__ __forceinline__ void dft_lds(double2* buf, const DftDev& d, const double2* tw, int t, int T) {
-    fft_lds<kMixed>(buf, d, tw, t, T);
-    if (!kMixed && d.bluestein) {
-        double2 bh[kPts];
+    fft_lds<kMode, kP>(buf, d, tw, t, T);
+    if (kMode == 0 && d.bluestein) {
+        double2 bh[kP];
 #pragma unroll
-        for (int c = 0; c < kPts; ++c) {
+        for (int c = 0; c < kP; ++c) {
             const int k = t + c * T;
             bh[c] = k < d.Nb ? d.bhat[k] : make_double2(0.0, 0.0);
         }
 #pragma unroll
-        for (int c = 0; c < kPts; ++c) {
+        for (int c = 0; c < kP; ++c) {
             const int k = t + c * T;
             if (k < d.Nb) buf[P(k)] = cconj(cmul(buf[P(k)], bh[c]));
         }
         __syncthreads();
-        fft_lds<false>(buf, d, tw, t, T);
+        fft_lds<0, kP>(buf, d, tw, t, T);
 #pragma unroll
-        for (int c = 0; c < kPts; ++c) {
+        for (int c = 0; c < kP; ++c) {
             const int k = t + c * T;
             bh[c] = k < d.L ? d.chirp[k] : make_double2(0.0, 0.0);
         }
 #pragma unroll
-        for (int c = 0; c < kPts; ++c) {
+        for (int c = 0; c < kP; ++c) {
             const int k = t + c * T;
             if (k < d.L) buf[P(k)] = cmul(cconj(buf[P(k)]), bh[c]);
         }
@@ -497,7 +498,7 @@ __device__ __forceinline__ int64_t line_group(int xcd) {
     return static_cast<int64_t>(x) * (G >> 3) + (x < rem ? x : rem) + (b >> 3);
 }
 
-template <bool kLineFast, bool kMixed>
+template <bool kLineFast, int kMode, int kP>
 __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, LineSet ls,
                                               int mlen, DftDev d,
                                               const double* __restrict__ pre,
@@ -515,8 +516,8 @@ __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, Li
     double2* buf = lds + d.Nb + li * line_stride(d.Nb);
     stage_twiddles(tws, d);
     const int M = mlen - 1;
-    // M + 1 <= Nb + 1 points: at most kPts + 1 per thread
-    constexpr int kIn = kPts + 1;
+    // M + 1 <= Nb + 1 points: at most kP + 1 per thread
+    constexpr int kIn = kP + 1;
     double2 y[kIn], fc[kIn];
     double ps[kIn];
 #pragma unroll
@@ -539,9 +540,9 @@ __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, Li
         }
     }
     __syncthreads();
-    double2 z[kPts];
+    double2 z[kP];
 #pragma unroll
-    for (int c = 0; c < kPts; ++c) {
+    for (int c = 0; c < kP; ++c) {
         const int j = t + c * TPL;
         if (j < M) {
             const double2 a = y[c], b = buf[P(M - j)];
@@ -551,19 +552,19 @@ __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, Li
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < kPts; ++c) {
+    for (int c = 0; c < kP; ++c) {
         const int j = t + c * TPL;
         if (j < M) buf[P(j)] = load_chirped(z[c], d, j);
     }
     for (int s = M + t; s < d.Nb; s += TPL) buf[P(s)] = make_double2(0.0, 0.0);
     __syncthreads();
-    dft_lds<kMixed>(buf, d, tws, t, TPL);
+    dft_lds<kMode, kP>(buf, d, tws, t, TPL);
     // even outputs (strided) and odd increments (contiguous chunk per thread)
     const int Ko = (M + 1) / 2;                 // odd outputs 1, 3, .., <= M
     const int Q = (Ko + TPL - 1) / TPL;
-    double2 ev[kPts / 2 + 1], dk[kPts / 2 + 1];
+    double2 ev[kP / 2 + 1], dk[kP / 2 + 1];
 #pragma unroll
-    for (int c = 0; c < kPts / 2 + 1; ++c) {
+    for (int c = 0; c < kP / 2 + 1; ++c) {
         const int k = t + c * TPL;
         ev[c] = make_double2(0.0, 0.0);
         if (2 * k <= M) {
@@ -572,7 +573,7 @@ __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, Li
         }
     }
 #pragma unroll
-    for (int q = 0; q < kPts / 2 + 1; ++q) {
+    for (int q = 0; q < kP / 2 + 1; ++q) {
         const int k = t * Q + q;
         dk[q] = make_double2(0.0, 0.0);
         if (q < Q && k >= 1 && k < Ko) {
@@ -581,9 +582,9 @@ __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, Li
         }
     }
 #pragma unroll
-    for (int q = 1; q < kPts / 2 + 1; ++q) dk[q] = make_double2(dk[q].x + dk[q - 1].x, dk[q].y + dk[q - 1].y);
+    for (int q = 1; q < kP / 2 + 1; ++q) dk[q] = make_double2(dk[q].x + dk[q - 1].x, dk[q].y + dk[q - 1].y);
     __syncthreads();
-    const double2 tot = dk[kPts / 2];
+    const double2 tot = dk[kP / 2];
     buf[P(t)] = tot;
     buf[P(TPL + t)] = f1;
     __syncthreads();
@@ -599,7 +600,7 @@ __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, Li
         // write it in order
         __syncthreads();
 #pragma unroll
-        for (int c = 0; c < kPts / 2 + 1; ++c) {
+        for (int c = 0; c < kP / 2 + 1; ++c) {
             const int k = t + c * TPL;
             if (2 * k <= M) {
                 const double sc = 2.0 * post[2 * k];
@@ -607,7 +608,7 @@ __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, Li
             }
         }
 #pragma unroll
-        for (int q = 0; q < kPts / 2 + 1; ++q) {
+        for (int q = 0; q < kP / 2 + 1; ++q) {
             const int k = t * Q + q;
             if (q < Q && k < Ko) {
                 const double sc = 2.0 * post[2 * k + 1];
@@ -619,7 +620,7 @@ __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, Li
             for (int s = t; s <= M; s += TPL) out[base + s * ls.elem] = buf[P(s)];
     } else if (valid) {
 #pragma unroll
-        for (int c = 0; c < kPts / 2 + 1; ++c) {
+        for (int c = 0; c < kP / 2 + 1; ++c) {
             const int k = t + c * TPL;
             if (2 * k <= M) {
                 const double sc = 2.0 * post[2 * k];
@@ -627,7 +628,7 @@ __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, Li
             }
         }
 #pragma unroll
-        for (int q = 0; q < kPts / 2 + 1; ++q) {
+        for (int q = 0; q < kP / 2 + 1; ++q) {
             const int k = t * Q + q;
             if (q < Q && k < Ko) {
                 const double sc = 2.0 * post[2 * k + 1];
@@ -640,7 +641,7 @@ __global__ __launch_bounds__(512) void k_dct(const double2* in, double2* out, Li
 
 // values [p][n][m] (real) -> planes [p/2+1][n][m] (complex): theta DFT with the
 // (-1)^w phase of theta_0 = -pi and the 1/p normalisation.
-template <bool kMixed>
+template <int kMode, int kP>
 __global__ __launch_bounds__(512) void k_theta_fwd(const double* __restrict__ val,
                                                     double2* __restrict__ planes, int m, int n,
                                                     int p, DftDev d, int TPL, int LPW) {
@@ -657,22 +658,22 @@ __global__ __launch_bounds__(512) void k_theta_fwd(const double* __restrict__ va
     double2* buf = lds + d.Nb + li * line_stride(d.Nb);
     stage_twiddles(tws, d);
     // every load of the thread is issued before the first is used (p <= Nb
-    // <= kPts TPL), so the HBM latency is paid once per line, not per point
-    double2 v[kPts];
+    // <= kP TPL), so the HBM latency is paid once per line, not per point
+    double2 v[kP];
 #pragma unroll
-    for (int c = 0; c < kPts; ++c) {
+    for (int c = 0; c < kP; ++c) {
         const int l = t + c * TPL;
         const int64_t off = (static_cast<int64_t>(l) * n + k) * m + j0;
         v[c] = make_double2(valid && l < p ? val[off] : 0.0, has1 && l < p ? val[off + 1] : 0.0);
     }
 #pragma unroll
-    for (int c = 0; c < kPts; ++c) {
+    for (int c = 0; c < kP; ++c) {
         const int l = t + c * TPL;
         if (l < p) buf[P(l)] = load_chirped(v[c], d, l);
     }
     for (int l = p + t; l < d.Nb; l += TPL) buf[P(l)] = make_double2(0.0, 0.0);
     __syncthreads();
-    dft_lds<kMixed>(buf, d, tws, t, TPL);
+    dft_lds<kMode, kP>(buf, d, tws, t, TPL);
     const int nw = p / 2 + 1;
     const double invp = 1.0 / p;
     for (int w = t; w < nw; w += TPL) {
@@ -690,7 +691,7 @@ __global__ __launch_bounds__(512) void k_theta_fwd(const double* __restrict__ va
 
 // planes -> values: f_l = sum_w Y_w e^{+2 pi i w l / p}, Y_w = (-1)^w c_w and
 // its Hermitian extension; two r-lines per complex inverse DFT.
-template <bool kMixed>
+template <int kMode, int kP>
 __global__ __launch_bounds__(512) void k_theta_inv(const double2* __restrict__ planes,
                                                     double* __restrict__ val, int m, int n, int p,
                                                     DftDev d, int TPL, int LPW) {
@@ -707,9 +708,9 @@ __global__ __launch_bounds__(512) void k_theta_inv(const double2* __restrict__ p
     double2* buf = lds + d.Nb + li * line_stride(d.Nb);
     stage_twiddles(tws, d);
     // all loads first (as in k_theta_fwd)
-    double2 va[kPts], vb[kPts];
+    double2 va[kP], vb[kP];
 #pragma unroll
-    for (int c = 0; c < kPts; ++c) {
+    for (int c = 0; c < kP; ++c) {
         const int l = t + c * TPL;
         const int wq = (2 * l <= p) ? l : p - l;
         const int64_t off = (static_cast<int64_t>(wq) * n + k) * m + j0;
@@ -717,7 +718,7 @@ __global__ __launch_bounds__(512) void k_theta_inv(const double2* __restrict__ p
         vb[c] = has1 && l < p ? planes[off + 1] : make_double2(0.0, 0.0);
     }
 #pragma unroll
-    for (int c = 0; c < kPts; ++c) {
+    for (int c = 0; c < kP; ++c) {
         const int l = t + c * TPL;
         if (l >= p) break;
         const int wq = (2 * l <= p) ? l : p - l;
@@ -732,7 +733,7 @@ __global__ __launch_bounds__(512) void k_theta_inv(const double2* __restrict__ p
     }
     for (int l = p + t; l < d.Nb; l += TPL) buf[P(l)] = make_double2(0.0, 0.0);
     __syncthreads();
-    dft_lds<kMixed>(buf, d, tws, t, TPL);
+    dft_lds<kMode, kP>(buf, d, tws, t, TPL);
     for (int l = t; l < p; l += TPL) {
         const double2 z = cconj(buf[P(l)]);
         const int64_t off = (static_cast<int64_t>(l) * n + k) * m + j0;
@@ -780,13 +781,36 @@ void line_config(int Nb, int tpl, bool strided, int* TPL, int* LPW, int* threads
     *lds = (static_cast<size_t>(*LPW) * line_stride(Nb) + Nb) * sizeof(double2);
 }
 
-// The mixed-radix kernels take lengths whose radix plan is not all powers
-// of two (never Bluestein).
-bool mixed_plan(const DftDev& d) {
-    if (d.bluestein) return false;
+// Kernel instance of a length (fft_lds): 0 powers of two (and Bluestein), 1
+// mixed radices, 2 mixed radices led by a prime pass.
+int dft_mode(const DftDev& d) {
+    if (d.bluestein) return 0;
+    if (d.nrad > 0 && d.rad[0] > 17) return 2;
     for (int i = 0; i < d.nrad; ++i)
-        if (d.rad[i] != 16 && d.rad[i] != 8 && d.rad[i] != 4 && d.rad[i] != 2) return true;
-    return false;
+        if (d.rad[i] != 16 && d.rad[i] != 8 && d.rad[i] != 4 && d.rad[i] != 2) return 1;
+    return 0;
+}
+
+template <int V>
+using IntC = std::integral_constant<int, V>;
+
+// Calls f(IntC<mode>, IntC<points per thread>) for the instance of the
+// length; a prime pass always runs with 16 points per thread.
+template <typename F>
+hipError_t dft_dispatch(const DftDev& d, F&& f) {
+    const int mode = dft_mode(d);
+    if (d.pts != 8 && d.pts != 16) return hipErrorInvalidValue;
+    if (mode == 2) {
+        if (d.pts != 16) return hipErrorInvalidValue;
+        f(IntC<2>{}, IntC<16>{});
+    } else if (mode == 1) {
+        if (d.pts == 8) f(IntC<1>{}, IntC<8>{});
+        else f(IntC<1>{}, IntC<16>{});
+    } else {
+        if (d.pts == 8) f(IntC<0>{}, IntC<8>{});
+        else f(IntC<0>{}, IntC<16>{});
+    }
+    return hipSuccess;
 }
 
 template <typename K>
@@ -805,14 +829,13 @@ hipError_t launch_theta_fwd(const double* values, double2* planes, int m, int n,
     line_config(d.Nb, d.tpl, true, &TPL, &LPW, &threads, &lds, true);
     const int64_t lines = static_cast<int64_t>(n) * ((m + 1) / 2);
     const unsigned grid = static_cast<unsigned>((lines + LPW - 1) / LPW);
-    if (mixed_plan(d)) {
-        raise_lds(k_theta_fwd<true>, lds);
-        hipLaunchKernelGGL(k_theta_fwd<true>, dim3(grid), dim3(threads), lds, s, values, planes, m, n, p, d, TPL, LPW);
-    } else {
-        raise_lds(k_theta_fwd<false>, lds);
-        hipLaunchKernelGGL(k_theta_fwd<false>, dim3(grid), dim3(threads), lds, s, values, planes, m, n, p, d, TPL, LPW);
-    }
-    return hipGetLastError();
+    const hipError_t e = dft_dispatch(d, [&](auto M, auto P) {
+        constexpr int kM = decltype(M)::value, kP = decltype(P)::value;
+        raise_lds(k_theta_fwd<kM, kP>, lds);
+        hipLaunchKernelGGL((k_theta_fwd<kM, kP>), dim3(grid), dim3(threads), lds, s, values, planes, m, n, p, d, TPL,
+                           LPW);
+    });
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_theta_inv(const double2* planes, double* values, int m, int n, int p,
@@ -822,14 +845,13 @@ hipError_t launch_theta_inv(const double2* planes, double* values, int m, int n,
     line_config(d.Nb, d.tpl, true, &TPL, &LPW, &threads, &lds, true);
     const int64_t lines = static_cast<int64_t>(n) * ((m + 1) / 2);
     const unsigned grid = static_cast<unsigned>((lines + LPW - 1) / LPW);
-    if (mixed_plan(d)) {
-        raise_lds(k_theta_inv<true>, lds);
-        hipLaunchKernelGGL(k_theta_inv<true>, dim3(grid), dim3(threads), lds, s, planes, values, m, n, p, d, TPL, LPW);
-    } else {
-        raise_lds(k_theta_inv<false>, lds);
-        hipLaunchKernelGGL(k_theta_inv<false>, dim3(grid), dim3(threads), lds, s, planes, values, m, n, p, d, TPL, LPW);
-    }
-    return hipGetLastError();
+    const hipError_t e = dft_dispatch(d, [&](auto M, auto P) {
+        constexpr int kM = decltype(M)::value, kP = decltype(P)::value;
+        raise_lds(k_theta_inv<kM, kP>, lds);
+        hipLaunchKernelGGL((k_theta_inv<kM, kP>), dim3(grid), dim3(threads), lds, s, planes, values, m, n, p, d, TPL,
+                           LPW);
+    });
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_dct(const double2* in, double2* out, const LineSet& ls, int mlen,
@@ -843,22 +865,19 @@ hipError_t launch_dct(const double2* in, double2* out, const LineSet& ls, int ml
     // strided line groups that split 128-byte lines: XCD-aware group order
     static const int kXcd = env_knob("CYLSPEC_DCT_XCD", 1);
     const int xcd = (kXcd != 0 && !contiguous_lines && (LPW * 16) % 128 != 0) ? 1 : 0;
-#define CYL_DCT(F, X)                                                                                 \
-    do {                                                                                              \
-        raise_lds(k_dct<F, X>, lds);                                                                  \
-        hipLaunchKernelGGL((k_dct<F, X>), dim3(grid), dim3(threads), lds, s, in, out, ls, mlen, d, pre, post, \
-                           fold, TPL, LPW, xcd);                                                      \
-    } while (0)
-    const bool mixed = mixed_plan(d);
-    if (contiguous_lines) {
-        if (mixed) CYL_DCT(false, true);
-        else CYL_DCT(false, false);
-    } else {
-        if (mixed) CYL_DCT(true, true);
-        else CYL_DCT(true, false);
-    }
-#undef CYL_DCT
-    return hipGetLastError();
+    const hipError_t e = dft_dispatch(d, [&](auto M, auto P) {
+        constexpr int kM = decltype(M)::value, kP = decltype(P)::value;
+        if (contiguous_lines) {
+            raise_lds(k_dct<false, kM, kP>, lds);
+            hipLaunchKernelGGL((k_dct<false, kM, kP>), dim3(grid), dim3(threads), lds, s, in, out, ls, mlen, d, pre,
+                               post, fold, TPL, LPW, xcd);
+        } else {
+            raise_lds(k_dct<true, kM, kP>, lds);
+            hipLaunchKernelGGL((k_dct<true, kM, kP>), dim3(grid), dim3(threads), lds, s, in, out, ls, mlen, d, pre,
+                               post, fold, TPL, LPW, xcd);
+        }
+    });
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 }  // namespace cyl
