@@ -93,3 +93,28 @@ def test_prime_pass_equals_bluestein(m, n, p):
     print("  fwd %.3e inv %.3e" % (np.max(np.abs(a - b)) / np.max(np.abs(b)), np.max(np.abs(ia - ib)) / np.max(np.abs(ib))))
     assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(b))
     assert np.max(np.abs(ia - ib)) < 1e-13 * np.max(np.abs(ib))
+
+
+@pytest.mark.parametrize("m,n,p", [(256, 36, 8), (36, 256, 96), (66, 10, 30), (17, 20, 256)])
+def test_sixteen_points_per_thread_match_oracle(m, n, p):
+    """The transform kernels exist for 8 and 16 points per thread; plans take
+    8 for direct lengths up to 256 without a prime pass (255 = 17 x 15,
+    35 = 7 x 5, 65 = 13 x 5, 96, 256, 30) and 16 otherwise.  The 16-point
+    instances of those lengths (CYLSPEC_DFT_POINTS=16) match the oracle too,
+    forward and inverse."""
+    import os
+    need_gpu()
+    banner("16 points per thread m=%d n=%d p=%d" % (m, n, p))
+    f = np.random.default_rng(m + 3 * n + 7 * p).standard_normal((p, n, m))
+    ref = tr.to_half(tr.forward(f))
+    os.environ["CYLSPEC_DFT_POINTS"] = "16"
+    try:
+        plan = cyl.Plan(m, n, p)
+        c = host(plan.transform_fwd(dev(f)))
+        v = host(plan.transform_inv(dev(ref)))
+    finally:
+        os.environ.pop("CYLSPEC_DFT_POINTS")
+    e1 = np.max(np.abs(c - ref)) / np.max(np.abs(ref))
+    e2 = np.max(np.abs(v - f)) / np.max(np.abs(f))
+    print("  fwd %.3e inv %.3e" % (e1, e2))
+    assert e1 < 1e-13 and e2 < 1e-13
