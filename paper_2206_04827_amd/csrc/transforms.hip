@@ -11,7 +11,10 @@
 // table is staged in LDS once per workgroup.  One larger prime factor (up to
 // 257) is taken as a direct first pass by all threads of a line together
 // (prime_pass); lengths with other factors go through Bluestein's chirp-z
-// identity with a power-of-two convolution.
+// identity with a power-of-two convolution.  The kernels are instantiated
+// per radix mode (powers of two, mixed radices, led by a prime pass) and
+// points per thread (8 or 16, chosen with the plan), so that each instance
+// holds only the registers its passes need.
 #include <type_traits>
 #include <cstdlib>
 
