@@ -1300,7 +1300,18 @@ __global__ __launch_bounds__(256) void k_recombine(const double* __restrict__ X,
                                                    const BlockDesc* __restrict__ blocks, int m,
                                                    int n) {
     __shared__ double2 xs[(kCL + 2) * kCS];
-    const int w = blockIdx.z, a0 = blockIdx.x * kCA, l0 = blockIdx.y * kCL;
+    // Tiles in XCD-aware order: workgroup b (linear, x fastest) runs on XCD
+    // b mod 8 and takes tile g = (b mod 8) G/8 + min(b mod 8, G mod 8) + b/8
+    // (a permutation of the G tiles), tiles counted with l fastest, so that
+    // neighbouring l-tiles, which read the same cache lines of the X rows,
+    // run on one XCD at about the same time.
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    const unsigned G = gx * gy * gridDim.z;
+    const unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned xcd = lin & 7u, rem = G & 7u;
+    const unsigned g = xcd * (G >> 3) + (xcd < rem ? xcd : rem) + (lin >> 3);
+    const int w = static_cast<int>(g / (gx * gy));
+    const int a0 = static_cast<int>((g / gy) % gx) * kCA, l0 = static_cast<int>(g % gy) * kCL;
     const int mi = m - 2, ni = n - 2, tid = threadIdx.x;
     const int p0 = plane_of[2 * w], p1 = plane_of[2 * w + 1];
     int64_t x0[4], x1[4];
