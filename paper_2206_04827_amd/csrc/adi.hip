@@ -1185,7 +1185,15 @@ __global__ __launch_bounds__(256) void k_rhs(const double2* __restrict__ F,
     double2* lt = gs + kRK * kRA;       // lift only: [kRL][kRA] L
     double2* gl = lt + kRL * kRA;       //            [kRK][kRA] L C02^T
     double2* ld = gl + kRK * kRA;       //            [kRK][kRA] L D2^T
-    const int w = blockIdx.z, i0 = blockIdx.x * kRI, k0 = blockIdx.y * kRK;
+    // Tiles in XCD-aware order (as in k_recombine): neighbouring tiles share
+    // their halo rows of F, and run on one XCD at about the same time.
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    const unsigned G = gx * gy * gridDim.z;
+    const unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned xcd = lin & 7u, rem = G & 7u;
+    const unsigned g = xcd * (G >> 3) + (xcd < rem ? xcd : rem) + (lin >> 3);
+    const int w = static_cast<int>(g / (gx * gy));
+    const int i0 = static_cast<int>((g / gy) % gx) * kRI, k0 = static_cast<int>(g % gy) * kRK;
     const int mi = m - 2, ni = n - 2, tid = threadIdx.x;
     const double2* Fw = F + static_cast<int64_t>(w) * n * m;
     const double2* Lw = kLift ? L + static_cast<int64_t>(w) * n * m : nullptr;
