@@ -79,8 +79,8 @@ STREAM_PASS_BYTES = 8 * 16.0
 # valid for the ADI source whose SHA-256 starts with ADI_TRAFFIC_SHA, at ADI
 # tolerance ADI_TRAFFIC_TOL (the traffic scales with the iteration count);
 # reported as null otherwise.
-ADI_TRAFFIC_BYTES_256 = 2.352e9
-ADI_TRAFFIC_SHA = "0fc84ac72c761bfd"
+ADI_TRAFFIC_BYTES_256 = 2.353e9
+ADI_TRAFFIC_SHA = "9ba3d375f39dbe70"
 ADI_TRAFFIC_TOL = 1e-10
 
 

@@ -1455,8 +1455,16 @@ __global__ __launch_bounds__(256) void k_apply(const BlockDesc* __restrict__ blo
                                                int me0, const double* __restrict__ ztabA, int ne0) {
     __shared__ double xs[kTR * kTS];
     __shared__ double zs[kTile * 8];
-    const BlockDesc bd = blocks[blockIdx.z];
-    const int i0 = blockIdx.x * kTile, k0 = blockIdx.y * kTile;
+    // Tiles in XCD-aware order (as in k_recombine), rows fastest: neighbouring
+    // tiles share halo rows and columns of X and run on one XCD at about the
+    // same time.
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    const unsigned G = gx * gy * gridDim.z;
+    const unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned xcd = lin & 7u, rem = G & 7u;
+    const unsigned g = xcd * (G >> 3) + (xcd < rem ? xcd : rem) + (lin >> 3);
+    const BlockDesc bd = blocks[g / (gx * gy)];
+    const int i0 = static_cast<int>(g % gx) * kTile, k0 = static_cast<int>((g / gx) % gy) * kTile;
     if (i0 >= bd.me || k0 >= bd.ne) return;
     apply_tile(xs, zs, bd, i0, k0, E, sE, X, sAB, sCD, out, atab, a_wstride, me0, ztabA, ne0);
 }
